@@ -1,0 +1,51 @@
+"""Shared test helpers: scenario builders and global-array assembly."""
+import numpy as np
+
+from paper_2403_15435_amd import inputs
+
+
+def row_scenario(n_cells, hL, uL, hR, uR, length=1000.0, m=16, t_end=1e300):
+    """One row of patches (y-invariant problem) with a jump at the middle."""
+    mi = n_cells // m
+    dx = length / n_cells
+    sc = inputs.Scenario(name="row", x0=0.0, y0=0.0, x1=length, y1=m * dx, mi=mi, mj=1, m=m,
+                         min_level=0, max_level=0, manning_n=0.0, t_end=t_end, init_level=0)
+    sc.dem = np.zeros((m + 1, mi * m + 1))
+    sc.dem_level = 0
+    x0 = 0.5 * length
+    sc.eta_fn = lambda X, Y, b: np.where(X < x0, hL, hR) + 0.0 * b
+    sc.uv_fn = lambda X, Y, h: (np.where(X < x0, hL * uL, hR * uR) + 0.0 * h, 0.0 * h)
+    return sc
+
+
+def assemble(sc, leaves, st, field, level=None):
+    """Global array [J][I] of one field for a uniform mesh (all leaves on one level)."""
+    lv = np.asarray(leaves)
+    if level is None:
+        level = int(lv[0, 1])
+    m = sc.m
+    NI = sc.mi * m << level
+    NJ = sc.mj * m << level
+    out = np.zeros((NJ, NI), dtype=st.dtype)
+    for k, (t, l, ix, iy) in enumerate(lv):
+        assert l == level
+        PI = (t % sc.mi) * (1 << l) + ix
+        PJ = (t // sc.mi) * (1 << l) + iy
+        out[PJ * m:(PJ + 1) * m, PI * m:(PI + 1) * m] = st[k, field]
+    return out
+
+
+def to_finest(sc, leaves, st, field, level):
+    """Piecewise-constant projection of an AMR field onto a uniform level."""
+    lv = np.asarray(leaves)
+    m = sc.m
+    NI = sc.mi * m << level
+    NJ = sc.mj * m << level
+    out = np.zeros((NJ, NI))
+    for k, (t, l, ix, iy) in enumerate(lv):
+        r = 1 << (level - l)
+        PI = (t % sc.mi) * (1 << l) + ix
+        PJ = (t // sc.mi) * (1 << l) + iy
+        blk = np.kron(st[k, field], np.ones((r, r)))
+        out[PJ * m * r:(PJ + 1) * m * r, PI * m * r:(PI + 1) * m * r] = blk
+    return out
