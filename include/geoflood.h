@@ -1,0 +1,186 @@
+/*
+ * geoflood.h -- C ABI of the MI355X shallow-water patch library.
+ *
+ * The library advances the 2D shallow-water equations with bathymetry and
+ * Manning friction (Kyanjo, Calhoun & George, GeoFlood v1.0.0, Section 3.1,
+ * eq. (shallow) and eq. (manning)) by the wave-propagation finite-volume
+ * method with an augmented Riemann solver, limited second-order corrections
+ * and transverse waves (Section 3.2, eqs. (wpa_update) and
+ * (wpa_update_corrections); Section 3.3), on a forest of quadtrees of
+ * fixed-size logically Cartesian patches (Section 4), with ghost cells filled
+ * from same-level, coarser and finer neighbours (Figure 1).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns GF_OK (0) or a negative GF_E_* status; a NULL
+ *     context gives GF_E_INVALID.  gf_last_error() describes the last failure.
+ *   - Host pointers are owned by the caller, read or written before the call
+ *     returns, and never kept.  The library owns all device memory it uses.
+ *   - All device work runs on the stream given at creation (NULL = the null
+ *     stream).  Functions that return host values synchronise that stream.
+ *   - One host thread at a time per context.
+ *   - Cell arrays are interior cells of one patch, row-major (j outer),
+ *     m x m values, FP64 at the ABI; an FP32 context rounds on the way in
+ *     (round to nearest even) and widens on the way out.
+ *   - Leaves of a scenario are ordered: trees row-major, then Z-order (x the
+ *     low bit) of each patch's lower-left corner within its tree.  A leaf is
+ *     described by 4 int32: (tree, level, ix, iy), ix, iy < 2^level.
+ *   - Fields: 0 depth h, 1 x-momentum hu, 2 y-momentum hv, 3 bed b.
+ */
+#ifndef GEOFLOOD_H
+#define GEOFLOOD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_ctx gf_ctx;
+
+enum {
+    GF_OK = 0,
+    GF_E_INVALID = -1,     /* bad argument or configuration                      */
+    GF_E_NOMEM = -2,       /* device or host allocation failed / pool too small  */
+    GF_E_HIP = -3,         /* a HIP runtime call failed                           */
+    GF_E_STATE = -4,       /* call out of order (e.g. step before bathymetry)    */
+    GF_E_CFL = -5,         /* a fixed step exceeded cfl_max; state kept at the last accepted step */
+    GF_E_NUMERIC = -6,     /* NaN/Inf produced; state kept at the last accepted step */
+    GF_E_UNSUPPORTED = -7  /* option not built (e.g. patch size)                 */
+};
+
+enum { GF_FP64 = 0, GF_FP32 = 1 };                     /* arithmetic of a context */
+enum { GF_BC_WALL = 0, GF_BC_EXTRAP = 1, GF_BC_INFLOW = 2 };
+
+/* One independent scenario (an ensemble member).  Sides: 0 x-low, 1 x-high,
+ * 2 y-low, 3 y-high. */
+typedef struct {
+    double x0, y0, x1, y1;       /* domain */
+    int32_t mi, mj;              /* trees in x and y (Section 4: m_i x m_j blocks) */
+    int32_t min_level, max_level;
+    double manning_n;            /* eq. (manning); 0 disables friction */
+    int32_t bc[4];               /* GF_BC_* per side */
+    int32_t inflow_side;         /* side carrying the inflow segment, or -1 */
+    double inflow_lo, inflow_hi; /* segment along that side (Section 4.1.1) */
+    const double *hydro;         /* n_hydro pairs (t [s], Q [m^3/s]), piecewise linear; copied */
+    int32_t n_hydro;             /* <= 16 */
+    double tag_h_refine;         /* depth refine threshold H_r [m] */
+    double tag_eta_refine;       /* free-surface difference threshold E_r [m] */
+    double t_end;                /* stop time; steps are truncated to reach it */
+} gf_scenario_desc;
+
+typedef struct {
+    int32_t precision;           /* GF_FP64 or GF_FP32 */
+    int32_t m;                   /* cells per patch side: 16 or 32 */
+    double g;                    /* gravity, 9.81 */
+    double dry_tol;              /* wet/dry threshold tau: dry iff h <= tau (1e-4 m) */
+    double cfl_desired;          /* target Courant number of the adaptive step (0.9) */
+    double cfl_max;              /* steps above this Courant number are rejected (1.0) */
+    int32_t n_scen;
+    const gf_scenario_desc *scen;
+    int64_t max_patches;         /* patch pool capacity over all scenarios */
+    void *hip_stream;            /* hipStream_t or NULL */
+} gf_config;
+
+typedef struct {
+    int64_t steps;               /* accepted steps over all scenarios in this call */
+    int64_t rejected;            /* rejected (retried) steps in this call */
+    int64_t cell_updates;        /* interior leaf cells x accepted steps */
+    double t_min, t_max;         /* scenario times after the call */
+    double dt_min, dt_max;       /* next step lengths after the call */
+} gf_step_stats;
+
+/* Create a context: validates the configuration and allocates the patch
+ * pool (state double-buffered, bathymetry, halo tables) on the device.
+ * Errors: GF_E_INVALID (bad m, levels, domain), GF_E_NOMEM, GF_E_HIP. */
+int gf_create(const gf_config *cfg, gf_ctx **out);
+void gf_destroy(gf_ctx *ctx);
+
+/* Bathymetry of scenario `scen` from terrain node values at the corners of
+ * the level-`dem_level` cells: dem_nodes[j * nx + i], nx = mi*m*2^dem_level+1,
+ * ny = mj*m*2^dem_level+1.  Cell values integrate the bilinear interpolant of
+ * the nodes (Section 5.3, integral-preserving topography): at levels >=
+ * dem_level the interpolant's cell average, below it the mean of the four
+ * children.  Errors: GF_E_INVALID on shape mismatch. */
+int gf_set_bathymetry(gf_ctx *ctx, int32_t scen, const double *dem_nodes, int64_t nx, int64_t ny,
+                      int32_t dem_level);
+
+/* Replace the mesh of a scenario by the given leaves (n rows of 4 int32, any
+ * order; stored in leaf order).  The leaves must tile the domain and be 2:1
+ * balanced across faces and corners.  State is zeroed; bathymetry is set.
+ * Errors: GF_E_INVALID (not a balanced tiling), GF_E_NOMEM (pool), GF_E_STATE
+ * (no bathymetry yet). */
+int gf_set_leaves(gf_ctx *ctx, int32_t scen, const int32_t *tlxy, int64_t n);
+/* Leaves of a scenario in leaf order; *n receives the count (also when cap is
+ * too small, which returns GF_E_INVALID). */
+int gf_get_leaves(gf_ctx *ctx, int32_t scen, int32_t *tlxy, int64_t cap, int64_t *n);
+
+/* One field of one leaf (interior, m*m values).  Fields 0..2 settable, 0..3
+ * readable. */
+int gf_set_patch(gf_ctx *ctx, int32_t scen, int64_t leaf, int32_t field, const double *in);
+int gf_get_patch(gf_ctx *ctx, int32_t scen, int64_t leaf, int32_t field, double *out);
+/* Whole scenario at once: n_leaves x 3 x m x m values (h, hu, hv per leaf). */
+int gf_set_state(gf_ctx *ctx, int32_t scen, const double *in);
+/* n_leaves x 4 x m x m values (h, hu, hv, b per leaf). */
+int gf_get_state(gf_ctx *ctx, int32_t scen, double *out);
+
+/* Fill the ghost layers (2 cells) of every leaf of every scenario at the
+ * current time, as the step does internally: same-level copies, averages of
+ * finer neighbours, limited interpolation from coarser neighbours, then the
+ * physical rules (wall mirror, extrapolation, inflow from eq. (riemann) /
+ * eq. (2-shock)).  The result is kept for gf_get_ghosted. */
+int gf_fill_ghosts(gf_ctx *ctx);
+/* (m+4)^2 values of one field of one leaf after gf_fill_ghosts, row-major,
+ * the first row being ghost row -2. */
+int gf_get_ghosted(gf_ctx *ctx, int32_t scen, int64_t leaf, int32_t field, double *out);
+
+/* Advance every scenario by nsteps accepted steps (or to its t_end).
+ * dt_fixed == NULL: adaptive steps, dt_{n+1} = dt_n cfl_desired / nu_n with
+ * nu the largest Courant number over all edges and levels; a step with
+ * nu > cfl_max is rejected and retried with dt cfl_desired / nu; the first
+ * step of a scenario comes from a speed-only pass.  dt_fixed != NULL: step k
+ * of this call uses dt_fixed[k] in every scenario, and nu > cfl_max returns
+ * GF_E_CFL.  Ghost filling, the update, friction, positivity and refluxing
+ * at coarse/fine faces all run inside.  `out` is nullable. */
+int gf_step(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
+
+/* Refinement flags of every leaf of every scenario, concatenated in scenario
+ * then leaf order: +1 refine, -1 coarsen, 0 keep (the depth, free-surface
+ * gradient and advancing-front criteria of Section 4, with halved thresholds
+ * for coarsening).  Decided in FP64 with + - and compares only.  `flags_out`
+ * is nullable (the flags are kept for gf_regrid). */
+int gf_tag(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
+
+/* Apply flags (NULL: those of the last gf_tag): refine, close under 2:1
+ * face+corner balance, coarsen complete families whose parent stays
+ * balanced; refinement by one level at a time (Section 4: no skipped
+ * levels).  Moves the data conservatively.  *n_leaves (nullable) receives
+ * the new total leaf count. */
+int gf_regrid(gf_ctx *ctx, const int8_t *flags_in, int64_t *n_leaves);
+
+/* Mass budget of a scenario: water volume sum(h dx dy) (compensated sum in
+ * leaf order), the volume added by resetting negative depths to zero, and the
+ * net volume that entered through non-wall physical boundaries. */
+int gf_mass(gf_ctx *ctx, int32_t scen, double *mass, double *clamp_volume, double *boundary_volume);
+
+/* Clock of a scenario. */
+int gf_time(gf_ctx *ctx, int32_t scen, double *t, double *dt_next, int64_t *steps, int64_t *rejected);
+int gf_set_time(gf_ctx *ctx, int32_t scen, double t, double dt_next);
+
+/* Time the step kernel with HIP events on the context stream: when enabled,
+ * every step-kernel launch is bracketed by events and gf_profile_read
+ * returns the number of launches and their summed duration (ms). */
+int gf_profile_enable(gf_ctx *ctx, int32_t on);
+int gf_profile_read(gf_ctx *ctx, int64_t *launches, double *ms_total);
+
+/* Description of the last failure on this context (static storage, valid
+ * until the next call on it). */
+const char *gf_last_error(const gf_ctx *ctx);
+
+/* Library version string. */
+const char *gf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEOFLOOD_H */

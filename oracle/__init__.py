@@ -57,7 +57,8 @@ def lib():
         L.orc_max_speed.restype = C.c_double
         L.orc_step.argtypes = [C.c_void_p, C.c_double]
         L.orc_step.restype = C.c_double
-        L.orc_advance.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_advance.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.orc_set_bathy_f32.argtypes = [C.c_void_p, C.c_int]
         L.orc_mass.argtypes = [C.c_void_p, _dp]
         L.orc_tag.argtypes = [C.c_void_p, C.POINTER(C.c_byte)]
         L.orc_regrid.argtypes = [C.c_void_p, C.POINTER(C.c_byte)]
@@ -166,17 +167,6 @@ class Oracle:
         lib().orc_get_ghosted(self._p, leaf, field, _d(out))
         return out
 
-    def set_initial(self, precision: str = "f64"):
-        """Initial state from the scenario's recipe on every leaf (b from the oracle's own pyramid)."""
-        from paper_2403_15435_amd.inputs import initial_state
-        lv = self.leaves()
-        for k in range(lv.shape[0]):
-            b = self.get_field(k, 3)
-            h, hu, hv = initial_state(self.sc, lv[k], b, precision)
-            self.set_field(k, 0, np.asarray(h, dtype=np.float64))
-            self.set_field(k, 1, np.asarray(hu, dtype=np.float64))
-            self.set_field(k, 2, np.asarray(hv, dtype=np.float64))
-
     def state(self) -> np.ndarray:
         """(n_leaves, 4, m, m) array of h, hu, hv, b."""
         n = self.n_leaves
@@ -202,17 +192,25 @@ class Oracle:
         """One step of length dt; returns max|s|/dx.  Does not advance the clock."""
         return lib().orc_step(self._p, dt)
 
-    def advance(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None):
-        """Advance with adaptive or fixed steps; returns the array of Courant numbers."""
+    def advance(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None, return_dt: bool = False):
+        """Advance with adaptive or fixed steps; returns the Courant numbers of the
+        accepted steps (and their lengths if return_dt)."""
         nu = np.zeros(max(nsteps, 1))
+        dts = np.zeros(max(nsteps, 1))
+        s0 = self.steps
         if dt_fixed is not None:
             d = np.ascontiguousarray(dt_fixed, dtype=np.float64)
-            rc = lib().orc_advance(self._p, nsteps, _d(d), _d(nu))
+            rc = lib().orc_advance(self._p, nsteps, _d(d), _d(nu), _d(dts))
         else:
-            rc = lib().orc_advance(self._p, nsteps, None, _d(nu))
+            rc = lib().orc_advance(self._p, nsteps, None, _d(nu), _d(dts))
         if rc != 0:
             raise RuntimeError(f"oracle advance failed ({rc})")
-        return nu
+        k = self.steps - s0
+        return (nu[:k], dts[:k]) if return_dt else nu[:k]
+
+    def set_bathy_f32(self, on: bool = True):
+        """Hold the bathymetry rounded to float32 (FP32-path judging)."""
+        lib().orc_set_bathy_f32(self._p, 1 if on else 0)
 
     @property
     def t(self) -> float:

@@ -86,6 +86,7 @@ typedef struct {
     long steps, rejected;
     double clamp_mass, bnd_mass;
     double m0;
+    int bathy_f32;       /* hold bathymetry rounded to float (to judge an FP32 run) */
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -335,8 +336,19 @@ static void leaf_bathymetry(orc_sim *s, leaf_t *L)
             long I = L->PI * m + i, J = L->PJ * m + j;
             if (I < 0 || I >= ni || J < 0 || J >= nj) continue;
             L->b[G(s, i, j)] = orc_bathy(s, L->level, I, J);
+            if (s->bathy_f32) L->b[G(s, i, j)] = (double)(float)L->b[G(s, i, j)];
         }
     physical_ghosts(s, L, &L->b, 1, 1);
+}
+
+/* Round every bathymetry value to the nearest float (and keep doing so after
+ * regrids): the FP32 library path is judged against FP64 arithmetic on the
+ * same rounded bed. */
+void orc_set_bathy_f32(orc_sim *s, int on)
+{
+    int k;
+    s->bathy_f32 = on;
+    for (k = 0; k < s->n_leaves; ++k) leaf_bathymetry(s, &s->leaves[k]);
 }
 
 static void leaf_alloc(orc_sim *s, leaf_t *L, int tree, int level, int ix, int iy)
@@ -1174,8 +1186,9 @@ double orc_step(orc_sim *s, double dt)
  * gives each step's length; otherwise dt_{n+1} = dt_n cfl_desired / nu_n,
  * truncated at t_end, and a step with nu > cfl_max is rejected and retried
  * with dt cfl_desired / nu.  Returns 0, or -5 if a fixed step exceeds
- * cfl_max (state left at the last accepted step). */
-int orc_advance(orc_sim *s, int nsteps, const double *dt_fixed, double *nu_out)
+ * cfl_max (state left at the last accepted step).  nu_out / dt_out
+ * (nullable) receive each accepted step's Courant number and length. */
+int orc_advance(orc_sim *s, int nsteps, const double *dt_fixed, double *nu_out, double *dt_out)
 {
     int m = s->m, n, k, f;
     size_t cells = (size_t)(m + 4) * (m + 4);
@@ -1207,6 +1220,7 @@ int orc_advance(orc_sim *s, int nsteps, const double *dt_fixed, double *nu_out)
             break;
         }
         if (nu_out) nu_out[n] = nu;
+        if (dt_out) dt_out[n] = dt;
         s->t += dt;
         s->steps++;
         s->dt = nu > 0.0 ? dt * s->cfl_desired / nu : dt;

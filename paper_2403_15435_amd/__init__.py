@@ -1,0 +1,274 @@
+"""MI355X shallow-water patch library (GeoFlood method) -- Python binding.
+
+Thin ctypes marshalling over the C ABI declared in include/geoflood.h; every
+step of the computation runs in the HIP library libgeoflood.so.  Importing
+this package fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgeoflood.so")
+
+GF_OK, GF_E_INVALID, GF_E_NOMEM, GF_E_HIP, GF_E_STATE, GF_E_CFL, GF_E_NUMERIC, GF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+GF_FP64, GF_FP32 = 0, 1
+_ERRNAME = {-1: "GF_E_INVALID", -2: "GF_E_NOMEM", -3: "GF_E_HIP", -4: "GF_E_STATE", -5: "GF_E_CFL",
+            -6: "GF_E_NUMERIC", -7: "GF_E_UNSUPPORTED"}
+
+
+class gf_scenario_desc(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("x1", C.c_double), ("y1", C.c_double),
+                ("mi", C.c_int32), ("mj", C.c_int32), ("min_level", C.c_int32), ("max_level", C.c_int32),
+                ("manning_n", C.c_double), ("bc", C.c_int32 * 4), ("inflow_side", C.c_int32),
+                ("inflow_lo", C.c_double), ("inflow_hi", C.c_double), ("hydro", C.POINTER(C.c_double)),
+                ("n_hydro", C.c_int32), ("tag_h_refine", C.c_double), ("tag_eta_refine", C.c_double),
+                ("t_end", C.c_double)]
+
+
+class gf_config(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("m", C.c_int32), ("g", C.c_double), ("dry_tol", C.c_double),
+                ("cfl_desired", C.c_double), ("cfl_max", C.c_double), ("n_scen", C.c_int32),
+                ("scen", C.POINTER(gf_scenario_desc)), ("max_patches", C.c_int64), ("hip_stream", C.c_void_p)]
+
+
+class gf_step_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("rejected", C.c_int64), ("cell_updates", C.c_int64),
+                ("t_min", C.c_double), ("t_max", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double)]
+
+
+EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
+           "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step",
+           "gf_tag", "gf_regrid", "gf_mass", "gf_time", "gf_set_time", "gf_profile_enable", "gf_profile_read",
+           "gf_last_error", "gf_version"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgeoflood.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2403_15435_amd.build.build()")
+    L = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.gf_create.argtypes = [C.POINTER(gf_config), C.POINTER(vp)]
+    L.gf_destroy.argtypes = [vp]
+    L.gf_destroy.restype = None
+    L.gf_set_bathymetry.argtypes = [vp, i32, dp, i64, i64, i32]
+    L.gf_set_leaves.argtypes = [vp, i32, C.POINTER(i32), i64]
+    L.gf_get_leaves.argtypes = [vp, i32, C.POINTER(i32), i64, C.POINTER(i64)]
+    L.gf_set_patch.argtypes = [vp, i32, i64, i32, dp]
+    L.gf_get_patch.argtypes = [vp, i32, i64, i32, dp]
+    L.gf_set_state.argtypes = [vp, i32, dp]
+    L.gf_get_state.argtypes = [vp, i32, dp]
+    L.gf_fill_ghosts.argtypes = [vp]
+    L.gf_get_ghosted.argtypes = [vp, i32, i64, i32, dp]
+    L.gf_step.argtypes = [vp, i32, dp, C.POINTER(gf_step_stats)]
+    L.gf_tag.argtypes = [vp, C.POINTER(C.c_int8), i64, C.POINTER(i64)]
+    L.gf_regrid.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(i64)]
+    L.gf_mass.argtypes = [vp, i32, dp, dp, dp]
+    L.gf_time.argtypes = [vp, i32, dp, dp, C.POINTER(i64), C.POINTER(i64)]
+    L.gf_set_time.argtypes = [vp, i32, C.c_double, C.c_double]
+    L.gf_profile_enable.argtypes = [vp, i32]
+    L.gf_profile_read.argtypes = [vp, C.POINTER(i64), dp]
+    L.gf_last_error.argtypes = [vp]
+    L.gf_last_error.restype = C.c_char_p
+    L.gf_version.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("gf_destroy", "gf_last_error", "gf_version"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class GFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAME.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream_handle():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return C.c_void_p(None)
+
+
+class Context:
+    """A library context over one or more scenarios (inputs.Scenario objects)."""
+
+    def __init__(self, scenarios: Sequence, precision: int = GF_FP64, max_patches: Optional[int] = None,
+                 g: float = 9.81, dry_tol: float = 1e-4, cfl_desired: float = 0.9, cfl_max: float = 1.0,
+                 stream=None):
+        L = load()
+        self.L = L
+        self.scenarios = list(scenarios)
+        self.m = self.scenarios[0].m
+        self.precision = precision
+        self._hydro = []
+        descs = (gf_scenario_desc * len(self.scenarios))()
+        for k, sc in enumerate(self.scenarios):
+            d = descs[k]
+            d.x0, d.y0, d.x1, d.y1 = sc.x0, sc.y0, sc.x1, sc.y1
+            d.mi, d.mj, d.min_level, d.max_level = sc.mi, sc.mj, sc.min_level, sc.max_level
+            d.manning_n = sc.manning_n
+            for s in range(4):
+                d.bc[s] = sc.bc[s]
+            d.inflow_side, d.inflow_lo, d.inflow_hi = sc.inflow_side, sc.inflow_lo, sc.inflow_hi
+            hy = np.ascontiguousarray(np.asarray(sc.hydro if sc.hydro else [(0.0, 0.0)], dtype=np.float64).reshape(-1))
+            self._hydro.append(hy)
+            d.hydro = _dptr(hy)
+            d.n_hydro = len(sc.hydro) if sc.hydro else 0
+            d.tag_h_refine, d.tag_eta_refine = sc.tag_h_refine, sc.tag_eta_refine
+            d.t_end = sc.t_end
+        if max_patches is None:
+            max_patches = 0
+            for sc in self.scenarios:
+                max_patches += sc.mi * sc.mj * 4 ** sc.max_level
+            max_patches = int(min(max_patches, 200000))
+        cfg = gf_config(precision=precision, m=self.m, g=g, dry_tol=dry_tol, cfl_desired=cfl_desired,
+                        cfl_max=cfl_max, n_scen=len(self.scenarios), scen=descs, max_patches=max_patches,
+                        hip_stream=stream if stream is not None else _stream_handle())
+        self._p = C.c_void_p()
+        rc = L.gf_create(C.byref(cfg), C.byref(self._p))
+        if rc != 0:
+            raise GFError(rc, "gf_create failed")
+        for k, sc in enumerate(self.scenarios):
+            if sc.dem is not None:
+                self.set_bathymetry(k, sc.dem, sc.dem_level)
+                self.set_leaves(k, sc.uniform_leaves(sc.init_level))
+
+    def _chk(self, rc: int):
+        if rc != 0:
+            raise GFError(rc, self.L.gf_last_error(self._p).decode())
+
+    def close(self):
+        if getattr(self, "_p", None):
+            self.L.gf_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- ABI
+    def set_bathymetry(self, scen: int, dem: np.ndarray, dem_level: int):
+        a = np.ascontiguousarray(dem, dtype=np.float64)
+        self._chk(self.L.gf_set_bathymetry(self._p, scen, _dptr(a), a.shape[1], a.shape[0], dem_level))
+
+    def set_leaves(self, scen: int, leaves: np.ndarray):
+        a = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+        self._chk(self.L.gf_set_leaves(self._p, scen, a.ctypes.data_as(C.POINTER(C.c_int32)), a.shape[0]))
+
+    def leaves(self, scen: int = 0) -> np.ndarray:
+        n = C.c_int64()
+        self._chk(self.L.gf_get_leaves(self._p, scen, None, 0, C.byref(n)))
+        out = np.zeros((n.value, 4), dtype=np.int32)
+        self._chk(self.L.gf_get_leaves(self._p, scen, out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)))
+        return out
+
+    def set_patch(self, scen: int, leaf: int, field: int, a: np.ndarray):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self._chk(self.L.gf_set_patch(self._p, scen, leaf, field, _dptr(a)))
+
+    def get_patch(self, scen: int, leaf: int, field: int) -> np.ndarray:
+        out = np.zeros((self.m, self.m))
+        self._chk(self.L.gf_get_patch(self._p, scen, leaf, field, _dptr(out)))
+        return out
+
+    def set_state(self, scen: int, st: np.ndarray):
+        a = np.ascontiguousarray(np.asarray(st, dtype=np.float64)[:, :3])
+        self._chk(self.L.gf_set_state(self._p, scen, _dptr(a)))
+
+    def state(self, scen: int = 0) -> np.ndarray:
+        n = self.leaves(scen).shape[0]
+        out = np.zeros((n, 4, self.m, self.m))
+        self._chk(self.L.gf_get_state(self._p, scen, _dptr(out)))
+        return out
+
+    def fill_ghosts(self):
+        self._chk(self.L.gf_fill_ghosts(self._p))
+
+    def ghosted(self, scen: int, leaf: int, field: int) -> np.ndarray:
+        out = np.zeros((self.m + 4, self.m + 4))
+        self._chk(self.L.gf_get_ghosted(self._p, scen, leaf, field, _dptr(out)))
+        return out
+
+    def step(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None) -> gf_step_stats:
+        st = gf_step_stats()
+        if dt_fixed is not None:
+            d = np.ascontiguousarray(dt_fixed, dtype=np.float64)
+            assert d.shape[0] >= nsteps
+            self._chk(self.L.gf_step(self._p, nsteps, _dptr(d), C.byref(st)))
+        else:
+            self._chk(self.L.gf_step(self._p, nsteps, None, C.byref(st)))
+        return st
+
+    def tag(self) -> np.ndarray:
+        n = C.c_int64()
+        self._chk(self.L.gf_tag(self._p, None, 0, C.byref(n)))
+        out = np.zeros(n.value, dtype=np.int8)
+        self._chk(self.L.gf_tag(self._p, out.ctypes.data_as(C.POINTER(C.c_int8)), n.value, C.byref(n)))
+        return out
+
+    def regrid(self, flags: Optional[np.ndarray] = None) -> int:
+        n = C.c_int64()
+        if flags is None:
+            self._chk(self.L.gf_regrid(self._p, None, C.byref(n)))
+        else:
+            f = np.ascontiguousarray(flags, dtype=np.int8)
+            self._chk(self.L.gf_regrid(self._p, f.ctypes.data_as(C.POINTER(C.c_int8)), C.byref(n)))
+        return n.value
+
+    def mass(self, scen: int = 0):
+        m, c, b = C.c_double(), C.c_double(), C.c_double()
+        self._chk(self.L.gf_mass(self._p, scen, C.byref(m), C.byref(c), C.byref(b)))
+        return np.array([m.value, c.value, b.value])
+
+    def time(self, scen: int = 0):
+        t, dt = C.c_double(), C.c_double()
+        s, r = C.c_int64(), C.c_int64()
+        self._chk(self.L.gf_time(self._p, scen, C.byref(t), C.byref(dt), C.byref(s), C.byref(r)))
+        return t.value, dt.value, s.value, r.value
+
+    def set_time(self, scen: int, t: float, dt_next: float = 0.0):
+        self._chk(self.L.gf_set_time(self._p, scen, t, dt_next))
+
+    def profile_enable(self, on: bool = True):
+        self._chk(self.L.gf_profile_enable(self._p, 1 if on else 0))
+
+    def profile_read(self):
+        n, ms = C.c_int64(), C.c_double()
+        self._chk(self.L.gf_profile_read(self._p, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    # ------------------------------------------------------------ helpers
+    def set_initial(self, scen: int = 0, precision: Optional[str] = None):
+        """Initial state from the scenario recipe, formed from this library's own bathymetry."""
+        from .inputs import initial_state
+        if precision is None:
+            precision = "f32" if self.precision == GF_FP32 else "f64"
+        sc = self.scenarios[scen]
+        lv = self.leaves(scen)
+        st = self.state(scen)
+        for k in range(lv.shape[0]):
+            h, hu, hv = initial_state(sc, lv[k], st[k, 3], precision)
+            st[k, 0], st[k, 1], st[k, 2] = h, hu, hv
+        self.set_state(scen, st)
+        return st

@@ -1,0 +1,1126 @@
+// Host core of the patch library: scenario forests, bathymetry pyramid, patch
+// pool, halo descriptors, regrid topology and the C ABI (include/geoflood.h).
+#include "../../include/geoflood.h"
+#include "gf_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+using namespace gf;
+
+namespace {
+
+constexpr int kMaxHydro = 16;
+
+struct Leaf {
+    int32_t level;
+    int64_t PI, PJ;   // global patch index at `level`
+    int32_t slot;
+};
+
+inline uint64_t key_of(int level, int64_t PI, int64_t PJ)
+{
+    return ((uint64_t)(level + 1) << 56) | ((uint64_t)PI << 28) | (uint64_t)PJ;
+}
+
+inline uint64_t interleave(uint64_t x, uint64_t y)
+{
+    uint64_t k = 0;
+    for (int b = 0; b < 31; ++b) k |= ((x >> b) & 1ull) << (2 * b) | ((y >> b) & 1ull) << (2 * b + 1);
+    return k;
+}
+
+struct Scen {
+    gf_scenario_desc d{};
+    std::vector<double> hydro;
+    int dem_level = -1;
+    int64_t dem_nx = 0, dem_ny = 0;
+    std::vector<double> dem;
+    std::vector<std::vector<double>> pyr;   // levels 0..dem_level
+    std::vector<Leaf> leaves;
+    std::unordered_map<uint64_t, int> map;  // key -> leaf index
+    double clamp_base = 0.0, bnd_base = 0.0;
+};
+
+}  // namespace
+
+struct gf_ctx {
+    gf_config cfg{};
+    int prec = GF_FP64;
+    int m = 32;
+    size_t es = 8;
+    hipStream_t stream = nullptr;
+    std::vector<Scen> sc;
+    int64_t cap = 0;
+    std::vector<int32_t> free_slots;
+    // device memory
+    void *q[2] = {nullptr, nullptr};
+    void *b = nullptr, *bg = nullptr, *reg = nullptr, *ghost = nullptr;
+    double *cacc[2] = {nullptr, nullptr}, *bacc[2] = {nullptr, nullptr};
+    PatchDesc *d_desc = nullptr;
+    int64_t desc_cap = 0;
+    RefluxTask *d_reflux = nullptr;
+    int64_t reflux_cap = 0;
+    ScenDev *d_scen = nullptr;
+    unsigned *d_counter = nullptr;
+    int8_t *d_flags = nullptr;
+    double *d_thr = nullptr, *d_mass = nullptr;
+    int32_t *d_lev = nullptr;
+    XferTaskH *d_xfer = nullptr;
+    int64_t xfer_cap = 0;
+    // host mirrors
+    std::vector<PatchDesc> desc;
+    std::vector<RefluxTask> reflux;
+    std::vector<ScenDev> hs;
+    std::vector<int8_t> last_flags;
+    bool topo_dirty = true;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0;
+    std::string err;
+};
+
+namespace {
+
+int fail(gf_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(gf_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(c, x)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail((c), GF_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+inline int64_t NI(const gf_ctx *c, const Scen &s, int l) { return (int64_t)s.d.mi * c->m << l; }
+inline int64_t NJ(const gf_ctx *c, const Scen &s, int l) { return (int64_t)s.d.mj * c->m << l; }
+inline double DXl(const gf_ctx *c, const Scen &s, int l) { return (s.d.x1 - s.d.x0) / (double)NI(c, s, l); }
+inline double DYl(const gf_ctx *c, const Scen &s, int l) { return (s.d.y1 - s.d.y0) / (double)NJ(c, s, l); }
+inline int ring_size(int m) { return (m + 4) * (m + 4) - m * m; }
+
+// ---------------------------------------------------------------- bathymetry
+// Cell bathymetry at level l, cell (I, J): integral of the bilinear terrain
+// interpolant over the cell (Section 5.3).  Four-point means pair diagonal
+// corners so that the result is invariant under exchange of the axes.
+double bathy(const gf_ctx *c, const Scen &s, int l, int64_t I, int64_t J)
+{
+    if (l < s.dem_level) return s.pyr[l][(size_t)(J * NI(c, s, l) + I)];
+    const int64_t r = (int64_t)1 << (l - s.dem_level);
+    const int64_t i0 = I / r, j0 = J / r;
+    auto N = [&](int64_t i, int64_t j) { return s.dem[(size_t)(j * s.dem_nx + i)]; };
+    const double n00 = N(i0, j0), n10 = N(i0 + 1, j0), n01 = N(i0, j0 + 1), n11 = N(i0 + 1, j0 + 1);
+    if (r == 1) return 0.25 * ((n00 + n11) + (n10 + n01));
+    const double fx = ((double)(I - i0 * r) + 0.5) / (double)r;
+    const double fy = ((double)(J - j0 * r) + 0.5) / (double)r;
+    const double w00 = (1.0 - fx) * (1.0 - fy), w11 = fx * fy, w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy;
+    return (n00 * w00 + n11 * w11) + (n10 * w10 + n01 * w01);
+}
+
+void build_pyramid(const gf_ctx *c, Scen &s)
+{
+    const int L = s.dem_level;
+    s.pyr.assign((size_t)L, {});
+    for (int l = L - 1; l >= 0; --l) {
+        const int64_t ni = NI(c, s, l), nj = NJ(c, s, l);
+        std::vector<double> &P = s.pyr[(size_t)l];
+        P.resize((size_t)(ni * nj));
+        for (int64_t J = 0; J < nj; ++J)
+            for (int64_t I = 0; I < ni; ++I) {
+                const double a = bathy(c, s, l + 1, 2 * I, 2 * J), d = bathy(c, s, l + 1, 2 * I + 1, 2 * J + 1);
+                const double e = bathy(c, s, l + 1, 2 * I + 1, 2 * J), f = bathy(c, s, l + 1, 2 * I, 2 * J + 1);
+                P[(size_t)(J * ni + I)] = 0.25 * ((a + d) + (e + f));
+            }
+    }
+}
+
+// (m+4)^2 bathymetry tile of a leaf: interior and ghost cells from the
+// pyramid at the leaf's level; outside the domain the physical rules (x rule,
+// then y rule): mirror for walls and inflow sides, copy for extrapolation.
+void leaf_bathy_tile(const gf_ctx *c, const Scen &s, const Leaf &L, std::vector<double> &t)
+{
+    const int m = c->m, TW = m + 4;
+    const int64_t ni = NI(c, s, L.level), nj = NJ(c, s, L.level);
+    t.assign((size_t)TW * TW, 0.0);
+    auto T = [&](int i, int j) -> double & { return t[(size_t)((j + 2) * TW + (i + 2))]; };
+    for (int j = -2; j < m + 2; ++j)
+        for (int i = -2; i < m + 2; ++i) {
+            const int64_t I = L.PI * m + i, J = L.PJ * m + j;
+            if (I < 0 || I >= ni || J < 0 || J >= nj) continue;
+            T(i, j) = bathy(c, s, L.level, I, J);
+        }
+    for (int j = -2; j < m + 2; ++j)
+        for (int i = -2; i < m + 2; ++i) {
+            const int64_t I = L.PI * m + i, J = L.PJ * m + j;
+            if (I >= 0 && I < ni) continue;
+            if (J < 0 || J >= nj) continue;
+            const int side = I < 0 ? 0 : 1, bc = s.d.bc[side];
+            int si;
+            if (bc == GF_BC_EXTRAP) si = side == 0 ? 0 : m - 1;
+            else si = side == 0 ? -1 - i : 2 * m - 1 - i;
+            T(i, j) = T(si, j);
+        }
+    for (int j = -2; j < m + 2; ++j)
+        for (int i = -2; i < m + 2; ++i) {
+            const int64_t J = L.PJ * m + j;
+            if (J >= 0 && J < nj) continue;
+            const int side = J < 0 ? 2 : 3, bc = s.d.bc[side];
+            int sj;
+            if (bc == GF_BC_EXTRAP) sj = side == 2 ? 0 : m - 1;
+            else sj = side == 2 ? -1 - j : 2 * m - 1 - j;
+            T(i, j) = T(i, sj);
+        }
+}
+
+template <typename R>
+void pack_bathy(const gf_ctx *c, const std::vector<double> &t, R *interior, R *ring)
+{
+    const int m = c->m, TW = m + 4;
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) interior[j * m + i] = (R)t[(size_t)((j + 2) * TW + (i + 2))];
+    int r = 0;
+    for (int j = -2; j < 0; ++j)
+        for (int i = -2; i < m + 2; ++i) ring[r++] = (R)t[(size_t)((j + 2) * TW + (i + 2))];
+    for (int j = m; j < m + 2; ++j)
+        for (int i = -2; i < m + 2; ++i) ring[r++] = (R)t[(size_t)((j + 2) * TW + (i + 2))];
+    const int cols[4] = {-2, -1, m, m + 1};
+    for (int cc = 0; cc < 4; ++cc)
+        for (int j = 0; j < m; ++j) ring[r++] = (R)t[(size_t)((j + 2) * TW + (cols[cc] + 2))];
+}
+
+int upload_bathy(gf_ctx *c, const Scen &s, const std::vector<Leaf *> &leaves)
+{
+    const int m = c->m, rs = ring_size(m);
+    const size_t MM = (size_t)m * m;
+    std::vector<double> tile;
+    std::vector<char> bi(c->es * MM), br(c->es * (size_t)rs);
+    for (Leaf *L : leaves) {
+        leaf_bathy_tile(c, s, *L, tile);
+        if (c->prec == GF_FP32) pack_bathy<float>(c, tile, (float *)bi.data(), (float *)br.data());
+        else pack_bathy<double>(c, tile, (double *)bi.data(), (double *)br.data());
+        HIPCHK(c, hipMemcpyAsync((char *)c->b + (size_t)L->slot * MM * c->es, bi.data(), bi.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync((char *)c->bg + (size_t)L->slot * rs * c->es, br.data(), br.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return GF_OK;
+}
+
+// ---------------------------------------------------------------- forest
+void sort_leaves(const gf_ctx *c, Scen &s)
+{
+    const int mi = s.d.mi;
+    std::sort(s.leaves.begin(), s.leaves.end(), [&](const Leaf &a, const Leaf &b) {
+        const int64_t ta = (a.PJ >> a.level) * mi + (a.PI >> a.level);
+        const int64_t tb = (b.PJ >> b.level) * mi + (b.PI >> b.level);
+        if (ta != tb) return ta < tb;
+        const uint64_t ka = interleave((uint64_t)(a.PI & ((1ll << a.level) - 1)) << (20 - a.level),
+                                       (uint64_t)(a.PJ & ((1ll << a.level) - 1)) << (20 - a.level));
+        const uint64_t kb = interleave((uint64_t)(b.PI & ((1ll << b.level) - 1)) << (20 - b.level),
+                                       (uint64_t)(b.PJ & ((1ll << b.level) - 1)) << (20 - b.level));
+        return ka < kb;
+    });
+    s.map.clear();
+    for (size_t k = 0; k < s.leaves.size(); ++k) s.map[key_of(s.leaves[k].level, s.leaves[k].PI, s.leaves[k].PJ)] = (int)k;
+    (void)c;
+}
+
+// leaf covering cell (l, I, J) of a scenario: rel 0 same, -1 coarser, +1 finer
+int cover(const gf_ctx *c, const Scen &s, int l, int64_t I, int64_t J, int &rel)
+{
+    const int m = c->m;
+    auto it = s.map.find(key_of(l, I / m, J / m));
+    if (it != s.map.end()) { rel = 0; return it->second; }
+    if (l > 0) {
+        it = s.map.find(key_of(l - 1, (I >> 1) / m, (J >> 1) / m));
+        if (it != s.map.end()) { rel = -1; return it->second; }
+    }
+    it = s.map.find(key_of(l + 1, (2 * I) / m, (2 * J) / m));
+    if (it != s.map.end()) { rel = 1; return it->second; }
+    return -1;
+}
+
+int32_t take_slot(gf_ctx *c)
+{
+    if (c->free_slots.empty()) return -1;
+    int32_t s = c->free_slots.back();
+    c->free_slots.pop_back();
+    return s;
+}
+
+void give_slot(gf_ctx *c, int32_t s) { c->free_slots.push_back(s); }
+
+// work list: PatchDesc per leaf (scenario order, leaf order) and reflux tasks
+int rebuild_work(gf_ctx *c)
+{
+    const int m = c->m;
+    c->desc.clear();
+    c->reflux.clear();
+    static const int reg_i0[12] = {-2, -2, 0, 0, 0, 0, 0, 0, -2, 0, -2, 0};
+    for (int si = 0; si < (int)c->sc.size(); ++si) {
+        Scen &s = c->sc[(size_t)si];
+        for (const Leaf &L : s.leaves) {
+            PatchDesc P{};
+            P.slot = L.slot; P.scen = si; P.level = L.level;
+            P.PI = (int32_t)L.PI; P.PJ = (int32_t)L.PJ;
+            const int64_t ni = NI(c, s, L.level), nj = NJ(c, s, L.level);
+            P.dx = DXl(c, s, L.level); P.dy = DYl(c, s, L.level);
+            P.xlo = s.d.x0 + (double)(L.PI * m) * P.dx;
+            P.ylo = s.d.y0 + (double)(L.PJ * m) * P.dy;
+            P.phys = (L.PI == 0 ? 1 : 0) | ((L.PI + 1) * m == ni ? 2 : 0) | (L.PJ == 0 ? 4 : 0) | ((L.PJ + 1) * m == nj ? 8 : 0);
+            for (int f = 0; f < 4; ++f) { P.bc[f] = s.d.bc[f]; P.cf_face[f] = -1; P.cf_role[f] = 0; }
+            (void)reg_i0;
+            for (int r = 0; r < 12; ++r) {
+                int i0, j0;
+                switch (r) {
+                case 0: i0 = -2; j0 = 0; break;
+                case 1: i0 = -2; j0 = m / 2; break;
+                case 2: i0 = m; j0 = 0; break;
+                case 3: i0 = m; j0 = m / 2; break;
+                case 4: i0 = 0; j0 = -2; break;
+                case 5: i0 = m / 2; j0 = -2; break;
+                case 6: i0 = 0; j0 = m; break;
+                case 7: i0 = m / 2; j0 = m; break;
+                case 8: i0 = -2; j0 = -2; break;
+                case 9: i0 = m; j0 = -2; break;
+                case 10: i0 = -2; j0 = m; break;
+                default: i0 = m; j0 = m; break;
+                }
+                const int64_t I = L.PI * m + i0, J = L.PJ * m + j0;
+                HaloSrc &h = P.src[r];
+                if (I < 0 || I >= ni || J < 0 || J >= nj) { h.kind = HK_PHYS; h.slot = -1; h.oi = h.oj = 0; continue; }
+                int rel;
+                const int k = cover(c, s, L.level, I, J, rel);
+                if (k < 0) return fail(c, GF_E_INVALID, "scenario %d: leaf (l%d,%lld,%lld) has an unbalanced or uncovered neighbour",
+                                       si, L.level, (long long)L.PI, (long long)L.PJ);
+                const Leaf &S = s.leaves[(size_t)k];
+                h.slot = S.slot;
+                if (rel == 0) { h.kind = HK_SAME; h.oi = (int32_t)((L.PI - S.PI) * m); h.oj = (int32_t)((L.PJ - S.PJ) * m); }
+                else if (rel == -1) { h.kind = HK_COARSE; h.oi = (int32_t)(L.PI * m - 2 * S.PI * m); h.oj = (int32_t)(L.PJ * m - 2 * S.PJ * m); }
+                else { h.kind = HK_FINE; h.oi = (int32_t)(2 * L.PI * m - S.PI * m); h.oj = (int32_t)(2 * L.PJ * m - S.PJ * m); }
+            }
+            for (int f = 0; f < 4; ++f) {
+                const HaloSrc &a = P.src[2 * f], &b2 = P.src[2 * f + 1];
+                if (a.kind == HK_FINE && b2.kind == HK_FINE) { P.cf_role[f] = 1; P.cf_face[f] = L.slot * 4 + f; }
+                else if (a.kind == HK_COARSE) { P.cf_role[f] = 2; P.cf_face[f] = L.slot * 4 + f; }
+                else if ((a.kind == HK_FINE) != (b2.kind == HK_FINE))
+                    return fail(c, GF_E_INVALID, "scenario %d: mixed-level face", si);
+            }
+            for (int f = 0; f < 4; ++f)
+                if (P.cf_role[f] == 1) {
+                    RefluxTask T{};
+                    T.slot = L.slot; T.scen = si; T.face = f; T.reg_c = L.slot * 4 + f;
+                    T.reg_f[0] = P.src[2 * f].slot * 4 + (f ^ 1);
+                    T.reg_f[1] = P.src[2 * f + 1].slot * 4 + (f ^ 1);
+                    T.half_f[0] = 0; T.half_f[1] = 1;
+                    T.area = P.dx * P.dy;
+                    c->reflux.push_back(T);
+                }
+            c->desc.push_back(P);
+        }
+    }
+    if ((int64_t)c->desc.size() > c->desc_cap) {
+        if (c->d_desc) (void)hipFree(c->d_desc);
+        if (c->d_flags) (void)hipFree(c->d_flags);
+        if (c->d_mass) (void)hipFree(c->d_mass);
+        c->desc_cap = std::max<int64_t>((int64_t)c->desc.size(), 1024);
+        HIPCHK(c, hipMalloc(&c->d_desc, sizeof(PatchDesc) * (size_t)c->desc_cap));
+        HIPCHK(c, hipMalloc(&c->d_flags, (size_t)c->desc_cap));
+        HIPCHK(c, hipMalloc(&c->d_mass, sizeof(double) * (size_t)c->desc_cap));
+    }
+    if ((int64_t)c->reflux.size() > c->reflux_cap) {
+        if (c->d_reflux) (void)hipFree(c->d_reflux);
+        c->reflux_cap = std::max<int64_t>((int64_t)c->reflux.size(), 256);
+        HIPCHK(c, hipMalloc(&c->d_reflux, sizeof(RefluxTask) * (size_t)c->reflux_cap));
+    }
+    if (!c->desc.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_desc, c->desc.data(), sizeof(PatchDesc) * c->desc.size(), hipMemcpyHostToDevice, c->stream));
+    if (!c->reflux.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_reflux, c->reflux.data(), sizeof(RefluxTask) * c->reflux.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->topo_dirty = false;
+    return GF_OK;
+}
+
+int push_scen(gf_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->d_scen, c->hs.data(), sizeof(ScenDev) * c->hs.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int pull_scen(gf_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->hs.data(), c->d_scen, sizeof(ScenDev) * c->hs.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int ensure_work(gf_ctx *c)
+{
+    if (c->topo_dirty) return rebuild_work(c);
+    return GF_OK;
+}
+
+// element access helpers for the state buffers
+inline size_t fstride(const gf_ctx *c) { return (size_t)c->cap * c->m * c->m; }
+
+int launch_step(gf_ctx *c, double dt_fixed, int mode)
+{
+    const int n = (int)c->desc.size();
+    hipError_t e;
+    const bool timed = c->prof && mode == 0;
+    size_t evk = 0;
+    if (timed) {
+        evk = (size_t)c->prof_launches * 2;
+        while (c->ev.size() < evk + 2) {
+            hipEvent_t x;
+            HIPCHK(c, hipEventCreate(&x));
+            c->ev.push_back(x);
+        }
+        HIPCHK(c, hipEventRecord(c->ev[evk], c->stream));
+    }
+    if (c->prec == GF_FP32) {
+        StepArgs<float> a{};
+        a.desc = c->d_desc; a.n_work = n; a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
+        a.q0 = (float *)c->q[0]; a.q1 = (float *)c->q[1]; a.b = (const float *)c->b; a.bg = (const float *)c->bg;
+        a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
+        a.reg = (float *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
+        a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
+        float tf = (float)c->cfg.dry_tol;
+        if ((double)tf > c->cfg.dry_tol) tf = std::nextafter(tf, 0.0f);
+        a.tau = tf; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = (float *)c->ghost;
+        e = gf_launch_step_f32(a, c->m, c->stream);
+    } else {
+        StepArgs<double> a{};
+        a.desc = c->d_desc; a.n_work = n; a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
+        a.q0 = (double *)c->q[0]; a.q1 = (double *)c->q[1]; a.b = (const double *)c->b; a.bg = (const double *)c->bg;
+        a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
+        a.reg = (double *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
+        a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
+        a.tau = c->cfg.dry_tol; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = (double *)c->ghost;
+        e = gf_launch_step_f64(a, c->m, c->stream);
+    }
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "step launch: %s", hipGetErrorString(e));
+    if (timed) {
+        HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
+        c->prof_launches++;
+    }
+    if (mode == 0 && !c->reflux.empty()) {
+        RefluxArgsBase r{};
+        r.tasks = c->d_reflux; r.n_tasks = (int)c->reflux.size(); r.scen = c->d_scen; r.cap = c->cap; r.tau64 = c->cfg.dry_tol;
+        if (c->prec == GF_FP32)
+            e = gf_launch_reflux_f32(r, (float *)c->q[0], (float *)c->q[1], (const float *)c->reg, c->cacc[0], c->cacc[1], c->m, c->stream);
+        else
+            e = gf_launch_reflux_f64(r, (double *)c->q[0], (double *)c->q[1], (const double *)c->reg, c->cacc[0], c->cacc[1], c->m, c->stream);
+        if (e != hipSuccess) return fail(c, GF_E_HIP, "reflux launch: %s", hipGetErrorString(e));
+    }
+    return GF_OK;
+}
+
+bool scen_ready(const Scen &s) { return s.dem_level >= 0 && !s.leaves.empty(); }
+
+// fold the per-slot clamp/boundary accumulators of the current buffer into
+// the scenario totals (leaf order) and clear them
+int fold_accumulators(gf_ctx *c)
+{
+    std::vector<double> ca((size_t)c->cap), ba((size_t)c->cap), cb((size_t)c->cap), bb((size_t)c->cap);
+    HIPCHK(c, hipMemcpyAsync(ca.data(), c->cacc[0], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cb.data(), c->cacc[1], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ba.data(), c->bacc[0], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bb.data(), c->bacc[1], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t si = 0; si < c->sc.size(); ++si) {
+        Scen &s = c->sc[si];
+        const int cur = c->hs[si].cur;
+        for (const Leaf &L : s.leaves) {
+            s.clamp_base += cur ? cb[(size_t)L.slot] : ca[(size_t)L.slot];
+            s.bnd_base += cur ? bb[(size_t)L.slot] : ba[(size_t)L.slot];
+        }
+    }
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(c, hipMemsetAsync(c->cacc[k], 0, sizeof(double) * (size_t)c->cap, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->bacc[k], 0, sizeof(double) * (size_t)c->cap, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int check_scen(gf_ctx *c, int32_t scen)
+{
+    if (!c) return GF_E_INVALID;
+    if (scen < 0 || scen >= (int32_t)c->sc.size()) return fail(c, GF_E_INVALID, "scenario %d out of range", scen);
+    return GF_OK;
+}
+
+template <typename R>
+void to_real(const double *in, R *out, size_t n) { for (size_t i = 0; i < n; ++i) out[i] = (R)in[i]; }
+template <typename R>
+void from_real(const R *in, double *out, size_t n) { for (size_t i = 0; i < n; ++i) out[i] = (double)in[i]; }
+
+}  // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+extern "C" {
+
+const char *gf_version(void) { return "geoflood-mi355x 0.1"; }
+
+const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int gf_create(const gf_config *cfg, gf_ctx **out)
+{
+    if (!cfg || !out) return GF_E_INVALID;
+    *out = nullptr;
+    if (cfg->m != 16 && cfg->m != 32) return GF_E_UNSUPPORTED;
+    if (cfg->precision != GF_FP32 && cfg->precision != GF_FP64) return GF_E_INVALID;
+    if (cfg->n_scen <= 0 || !cfg->scen || cfg->max_patches <= 0) return GF_E_INVALID;
+    if (!(cfg->g > 0) || !(cfg->dry_tol > 0) || !(cfg->cfl_desired > 0) || !(cfg->cfl_max >= cfg->cfl_desired)) return GF_E_INVALID;
+    gf_ctx *c = new gf_ctx();
+    c->cfg = *cfg;
+    c->cfg.scen = nullptr;
+    c->prec = cfg->precision;
+    c->m = cfg->m;
+    c->es = c->prec == GF_FP32 ? 4 : 8;
+    c->stream = (hipStream_t)cfg->hip_stream;
+    c->cap = cfg->max_patches;
+    c->sc.resize((size_t)cfg->n_scen);
+    c->hs.assign((size_t)cfg->n_scen, ScenDev{});
+    for (int i = 0; i < cfg->n_scen; ++i) {
+        const gf_scenario_desc &d = cfg->scen[i];
+        if (d.mi <= 0 || d.mj <= 0 || d.min_level < 0 || d.max_level < d.min_level || d.max_level > 14 ||
+            !(d.x1 > d.x0) || !(d.y1 > d.y0) || d.n_hydro < 0 || d.n_hydro > kMaxHydro ||
+            (d.n_hydro > 0 && !d.hydro)) {
+            delete c;
+            return GF_E_INVALID;
+        }
+        Scen &s = c->sc[(size_t)i];
+        s.d = d;
+        s.hydro.assign(d.hydro ? d.hydro : nullptr, d.hydro ? d.hydro + 2 * d.n_hydro : nullptr);
+        s.d.hydro = nullptr;
+        ScenDev &h = c->hs[(size_t)i];
+        h.t = 0.0; h.dt = 0.0; h.t_end = d.t_end; h.manning_n = d.manning_n;
+        h.inflow_lo = d.inflow_lo; h.inflow_hi = d.inflow_hi; h.inflow_side = d.inflow_side;
+        h.n_hydro = d.n_hydro;
+        for (int k = 0; k < d.n_hydro; ++k) { h.hydro_t[k] = d.hydro[2 * k]; h.hydro_q[k] = d.hydro[2 * k + 1]; }
+    }
+    for (int64_t k = c->cap - 1; k >= 0; --k) c->free_slots.push_back((int32_t)k);
+    const size_t MM = (size_t)c->m * c->m;
+    auto alloc = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        return hipMemset(*p, 0, bytes) == hipSuccess;
+    };
+    bool ok = true;
+    ok = ok && alloc(&c->q[0], 3 * MM * c->cap * c->es) && alloc(&c->q[1], 3 * MM * c->cap * c->es);
+    ok = ok && alloc(&c->b, MM * c->cap * c->es) && alloc(&c->bg, (size_t)ring_size(c->m) * c->cap * c->es);
+    ok = ok && alloc(&c->reg, (size_t)4 * c->cap * c->m * 3 * c->es);
+    ok = ok && alloc((void **)&c->cacc[0], sizeof(double) * c->cap) && alloc((void **)&c->cacc[1], sizeof(double) * c->cap);
+    ok = ok && alloc((void **)&c->bacc[0], sizeof(double) * c->cap) && alloc((void **)&c->bacc[1], sizeof(double) * c->cap);
+    ok = ok && alloc((void **)&c->d_scen, sizeof(ScenDev) * c->sc.size()) && alloc((void **)&c->d_counter, 64);
+    ok = ok && alloc((void **)&c->d_thr, sizeof(double) * 2 * c->sc.size()) && alloc((void **)&c->d_lev, sizeof(int32_t) * 2 * c->sc.size());
+    if (!ok) {
+        gf_destroy(c);
+        return GF_E_NOMEM;
+    }
+    std::vector<double> thr;
+    std::vector<int32_t> lev;
+    for (auto &s : c->sc) {
+        thr.push_back(s.d.tag_h_refine); thr.push_back(s.d.tag_eta_refine);
+        lev.push_back(s.d.min_level); lev.push_back(s.d.max_level);
+    }
+    if (hipMemcpy(c->d_thr, thr.data(), sizeof(double) * thr.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_lev, lev.data(), sizeof(int32_t) * lev.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        push_scen(c) != GF_OK) {
+        gf_destroy(c);
+        return GF_E_HIP;
+    }
+    *out = c;
+    return GF_OK;
+}
+
+void gf_destroy(gf_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
+                  c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int gf_set_bathymetry(gf_ctx *c, int32_t scen, const double *dem, int64_t nx, int64_t ny, int32_t dem_level)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    Scen &s = c->sc[(size_t)scen];
+    if (!dem || dem_level < 0 || dem_level > 14) return fail(c, GF_E_INVALID, "bad terrain arguments");
+    if (nx != NI(c, s, dem_level) + 1 || ny != NJ(c, s, dem_level) + 1)
+        return fail(c, GF_E_INVALID, "terrain %lldx%lld does not match level %d (%lldx%lld nodes)", (long long)nx,
+                    (long long)ny, dem_level, (long long)NI(c, s, dem_level) + 1, (long long)NJ(c, s, dem_level) + 1);
+    s.dem_level = dem_level;
+    s.dem_nx = nx;
+    s.dem_ny = ny;
+    s.dem.assign(dem, dem + nx * ny);
+    build_pyramid(c, s);
+    if (!s.leaves.empty()) {
+        std::vector<Leaf *> all;
+        for (auto &L : s.leaves) all.push_back(&L);
+        return upload_bathy(c, s, all);
+    }
+    return GF_OK;
+}
+
+int gf_set_leaves(gf_ctx *c, int32_t scen, const int32_t *tlxy, int64_t n)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    Scen &s = c->sc[(size_t)scen];
+    if (s.dem_level < 0) return fail(c, GF_E_STATE, "set the bathymetry first");
+    if (!tlxy || n <= 0) return fail(c, GF_E_INVALID, "no leaves");
+    // validate the tiling: area per tree sums to one, no leaf inside another
+    std::vector<Leaf> nl((size_t)n);
+    std::unordered_set<uint64_t> keys;
+    std::vector<double> area((size_t)s.d.mi * s.d.mj, 0.0);
+    for (int64_t k = 0; k < n; ++k) {
+        const int32_t t = tlxy[4 * k], l = tlxy[4 * k + 1], ix = tlxy[4 * k + 2], iy = tlxy[4 * k + 3];
+        if (t < 0 || t >= s.d.mi * s.d.mj || l < s.d.min_level || l > s.d.max_level || ix < 0 || iy < 0 ||
+            ix >= (1 << l) || iy >= (1 << l))
+            return fail(c, GF_E_INVALID, "leaf %lld out of range", (long long)k);
+        Leaf &L = nl[(size_t)k];
+        L.level = l;
+        L.PI = (int64_t)(t % s.d.mi) * (1ll << l) + ix;
+        L.PJ = (int64_t)(t / s.d.mi) * (1ll << l) + iy;
+        if (!keys.insert(key_of(l, L.PI, L.PJ)).second) return fail(c, GF_E_INVALID, "duplicate leaf");
+        area[(size_t)t] += std::ldexp(1.0, -2 * l);
+    }
+    for (const Leaf &L : nl)
+        for (int a = L.level - 1; a >= 0; --a)
+            if (keys.count(key_of(a, L.PI >> (L.level - a), L.PJ >> (L.level - a))))
+                return fail(c, GF_E_INVALID, "overlapping leaves");
+    for (double a : area)
+        if (a != 1.0) return fail(c, GF_E_INVALID, "leaves do not tile every tree");
+    if ((int64_t)c->free_slots.size() + (int64_t)s.leaves.size() < n) return fail(c, GF_E_NOMEM, "patch pool too small");
+    for (const Leaf &L : s.leaves) give_slot(c, L.slot);
+    s.leaves = nl;
+    for (Leaf &L : s.leaves) L.slot = take_slot(c);
+    sort_leaves(c, s);
+    // zero the state of the new slots in both buffers
+    const size_t MM = (size_t)c->m * c->m;
+    for (const Leaf &L : s.leaves)
+        for (int bf = 0; bf < 2; ++bf)
+            for (int f = 0; f < 3; ++f)
+                HIPCHK(c, hipMemsetAsync((char *)c->q[bf] + ((size_t)f * fstride(c) + (size_t)L.slot * MM) * c->es, 0, MM * c->es, c->stream));
+    std::vector<Leaf *> all;
+    for (auto &L : s.leaves) all.push_back(&L);
+    rc = upload_bathy(c, s, all);
+    if (rc) return rc;
+    c->topo_dirty = true;
+    rc = ensure_work(c);
+    if (rc) { c->topo_dirty = true; return rc; }
+    s.clamp_base = 0.0;
+    s.bnd_base = 0.0;
+    return GF_OK;
+}
+
+int gf_get_leaves(gf_ctx *c, int32_t scen, int32_t *tlxy, int64_t cap, int64_t *n)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    const Scen &s = c->sc[(size_t)scen];
+    if (n) *n = (int64_t)s.leaves.size();
+    if (!tlxy) return GF_OK;
+    if (cap < (int64_t)s.leaves.size()) return fail(c, GF_E_INVALID, "leaf buffer too small");
+    for (size_t k = 0; k < s.leaves.size(); ++k) {
+        const Leaf &L = s.leaves[k];
+        const int64_t ti = L.PI >> L.level, tj = L.PJ >> L.level;
+        tlxy[4 * k] = (int32_t)(tj * s.d.mi + ti);
+        tlxy[4 * k + 1] = L.level;
+        tlxy[4 * k + 2] = (int32_t)(L.PI - (ti << L.level));
+        tlxy[4 * k + 3] = (int32_t)(L.PJ - (tj << L.level));
+    }
+    return GF_OK;
+}
+
+static int patch_io(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, double *buf, bool write)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    const Scen &s = c->sc[(size_t)scen];
+    if (leaf < 0 || leaf >= (int64_t)s.leaves.size()) return fail(c, GF_E_INVALID, "leaf out of range");
+    if (field < 0 || field > 3 || (write && field == 3)) return fail(c, GF_E_INVALID, "bad field");
+    if (!buf) return GF_E_INVALID;
+    const size_t MM = (size_t)c->m * c->m;
+    const int slot = s.leaves[(size_t)leaf].slot;
+    const int cur = c->hs[(size_t)scen].cur;
+    char *dev = field == 3 ? (char *)c->b + (size_t)slot * MM * c->es
+                           : (char *)c->q[cur] + ((size_t)field * fstride(c) + (size_t)slot * MM) * c->es;
+    std::vector<char> tmp(MM * c->es);
+    if (write) {
+        if (c->prec == GF_FP32) to_real<float>(buf, (float *)tmp.data(), MM);
+        else to_real<double>(buf, (double *)tmp.data(), MM);
+        HIPCHK(c, hipMemcpyAsync(dev, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(tmp.data(), dev, tmp.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->prec == GF_FP32) from_real<float>((const float *)tmp.data(), buf, MM);
+        else from_real<double>((const double *)tmp.data(), buf, MM);
+    }
+    return GF_OK;
+}
+
+int gf_set_patch(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, const double *in)
+{
+    return patch_io(c, scen, leaf, field, const_cast<double *>(in), true);
+}
+
+int gf_get_patch(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, double *out)
+{
+    return patch_io(c, scen, leaf, field, out, false);
+}
+
+int gf_set_state(gf_ctx *c, int32_t scen, const double *in)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    if (!in) return GF_E_INVALID;
+    const Scen &s = c->sc[(size_t)scen];
+    const size_t MM = (size_t)c->m * c->m;
+    const int cur = c->hs[(size_t)scen].cur;
+    std::vector<char> tmp(MM * c->es);
+    for (size_t k = 0; k < s.leaves.size(); ++k)
+        for (int f = 0; f < 3; ++f) {
+            const double *src = in + (k * 3 + (size_t)f) * MM;
+            if (c->prec == GF_FP32) to_real<float>(src, (float *)tmp.data(), MM);
+            else to_real<double>(src, (double *)tmp.data(), MM);
+            char *dev = (char *)c->q[cur] + ((size_t)f * fstride(c) + (size_t)s.leaves[k].slot * MM) * c->es;
+            HIPCHK(c, hipMemcpyAsync(dev, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    return GF_OK;
+}
+
+int gf_get_state(gf_ctx *c, int32_t scen, double *out)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    if (!out) return GF_E_INVALID;
+    const Scen &s = c->sc[(size_t)scen];
+    const size_t MM = (size_t)c->m * c->m;
+    const int cur = c->hs[(size_t)scen].cur;
+    // copy whole buffers once, then gather
+    std::vector<char> qh(3 * fstride(c) * c->es), bh(MM * (size_t)c->cap * c->es);
+    HIPCHK(c, hipMemcpyAsync(qh.data(), c->q[cur], qh.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bh.data(), c->b, bh.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < s.leaves.size(); ++k) {
+        const size_t slot = (size_t)s.leaves[k].slot;
+        for (int f = 0; f < 4; ++f) {
+            double *dst = out + (k * 4 + (size_t)f) * MM;
+            const char *src = f < 3 ? qh.data() + ((size_t)f * fstride(c) + slot * MM) * c->es : bh.data() + slot * MM * c->es;
+            if (c->prec == GF_FP32) from_real<float>((const float *)src, dst, MM);
+            else from_real<double>((const double *)src, dst, MM);
+        }
+    }
+    return GF_OK;
+}
+
+int gf_fill_ghosts(gf_ctx *c)
+{
+    if (!c) return GF_E_INVALID;
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    const size_t TW = (size_t)c->m + 4;
+    if (!c->ghost) HIPCHK(c, hipMalloc(&c->ghost, (size_t)c->cap * 4 * TW * TW * c->es));
+    rc = launch_step(c, -1.0, 2);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int gf_get_ghosted(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, double *out)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    if (!c->ghost) return fail(c, GF_E_STATE, "call gf_fill_ghosts first");
+    const Scen &s = c->sc[(size_t)scen];
+    if (leaf < 0 || leaf >= (int64_t)s.leaves.size() || field < 0 || field > 3 || !out) return GF_E_INVALID;
+    const size_t TW2 = ((size_t)c->m + 4) * ((size_t)c->m + 4);
+    std::vector<char> tmp(TW2 * c->es);
+    const char *dev = (const char *)c->ghost + ((size_t)s.leaves[(size_t)leaf].slot * 4 + (size_t)field) * TW2 * c->es;
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), dev, tmp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->prec == GF_FP32) from_real<float>((const float *)tmp.data(), out, TW2);
+    else from_real<double>((const double *)tmp.data(), out, TW2);
+    return GF_OK;
+}
+
+int gf_step(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *out)
+{
+    if (!c) return GF_E_INVALID;
+    if (nsteps < 0) return fail(c, GF_E_INVALID, "negative step count");
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    std::vector<int64_t> steps0(c->hs.size()), rej0(c->hs.size());
+    for (size_t i = 0; i < c->hs.size(); ++i) {
+        ScenDev &h = c->hs[i];
+        h.status = 0;
+        h.target = h.steps + nsteps;
+        steps0[i] = h.steps;
+        rej0[i] = h.rejected;
+    }
+    rc = push_scen(c);
+    if (rc) return rc;
+    if (!dt_fixed) {
+        bool need = false;
+        for (auto &h : c->hs) need = need || h.dt <= 0.0;
+        if (need) {
+            rc = launch_step(c, -1.0, 1);
+            if (rc) return rc;
+        }
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        rc = launch_step(c, dt_fixed ? dt_fixed[k] : -1.0, 0);
+        if (rc) return rc;
+    }
+    rc = pull_scen(c);
+    if (rc) return rc;
+    if (!dt_fixed) {
+        // rejected attempts leave scenarios short of their target: keep going
+        for (int round = 0; round < 64; ++round) {
+            int64_t missing = 0;
+            for (auto &h : c->hs)
+                if (h.status == 0 && h.t < h.t_end) missing = std::max<int64_t>(missing, h.target - h.steps);
+            if (missing <= 0) break;
+            for (int64_t k = 0; k < missing; ++k) {
+                rc = launch_step(c, -1.0, 0);
+                if (rc) return rc;
+            }
+            rc = pull_scen(c);
+            if (rc) return rc;
+        }
+    }
+    int status = GF_OK;
+    gf_step_stats st{};
+    st.t_min = 1e300; st.t_max = -1e300; st.dt_min = 1e300; st.dt_max = -1e300;
+    for (size_t i = 0; i < c->hs.size(); ++i) {
+        const ScenDev &h = c->hs[i];
+        if (h.status != 0 && status == GF_OK) status = h.status;
+        st.steps += h.steps - steps0[i];
+        st.rejected += h.rejected - rej0[i];
+        int64_t cells = 0;
+        for (size_t k = 0; k < c->sc[i].leaves.size(); ++k) cells += (int64_t)c->m * c->m;
+        st.cell_updates += (h.steps - steps0[i]) * cells;
+        st.t_min = std::min(st.t_min, h.t); st.t_max = std::max(st.t_max, h.t);
+        st.dt_min = std::min(st.dt_min, h.dt); st.dt_max = std::max(st.dt_max, h.dt);
+    }
+    if (out) *out = st;
+    if (status == -5) return fail(c, GF_E_CFL, "a fixed step exceeded the maximum Courant number");
+    if (status == -6) return fail(c, GF_E_NUMERIC, "non-finite state produced");
+    return status;
+}
+
+int gf_tag(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n)
+{
+    if (!c) return GF_E_INVALID;
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    const int nw = (int)c->desc.size();
+    hipError_t e;
+    if (c->prec == GF_FP32)
+        e = gf_launch_tag_f32(c->d_desc, nw, c->d_scen, (const float *)c->q[0], (const float *)c->q[1], (const float *)c->b,
+                              c->cap, c->d_thr, c->d_lev, c->cfg.dry_tol, c->d_flags, c->m, c->stream);
+    else
+        e = gf_launch_tag_f64(c->d_desc, nw, c->d_scen, (const double *)c->q[0], (const double *)c->q[1], (const double *)c->b,
+                              c->cap, c->d_thr, c->d_lev, c->cfg.dry_tol, c->d_flags, c->m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "tag launch: %s", hipGetErrorString(e));
+    c->last_flags.resize((size_t)nw);
+    if (nw) HIPCHK(c, hipMemcpyAsync(c->last_flags.data(), c->d_flags, (size_t)nw, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (n) *n = nw;
+    if (flags_out) {
+        if (cap < nw) return fail(c, GF_E_INVALID, "flag buffer too small");
+        std::memcpy(flags_out, c->last_flags.data(), (size_t)nw);
+    }
+    return GF_OK;
+}
+
+// ------------------------------------------------------------------ regrid
+namespace {
+
+// Is the level-(l) cell position (X, Y) (in patch units) an interior node of
+// the tree described by `internal`?  Positions outside the domain are not.
+struct Topo {
+    const gf_ctx *c;
+    const Scen *s;
+    std::unordered_set<uint64_t> internal;   // keys of nodes that have children
+    bool inside(int l, int64_t X, int64_t Y) const
+    {
+        return X >= 0 && Y >= 0 && X < ((int64_t)s->d.mi << l) && Y < ((int64_t)s->d.mj << l);
+    }
+    void add_ancestors(int l, int64_t X, int64_t Y)
+    {
+        for (int a = l - 1; a >= 0; --a) {
+            const uint64_t k = key_of(a, X >> (l - a), Y >> (l - a));
+            if (!internal.insert(k).second) break;
+        }
+    }
+    // any leaf finer than level l+1 touching the level-l patch (X, Y)?  That is
+    // one of its twelve level-(l+1) neighbours being subdivided.
+    bool finer_than_next(int l, int64_t X, int64_t Y) const
+    {
+        const int64_t x0 = 2 * X, y0 = 2 * Y;
+        static const int off[12][2] = {{-1, 0}, {-1, 1}, {2, 0}, {2, 1}, {0, -1}, {1, -1}, {0, 2}, {1, 2},
+                                       {-1, -1}, {2, -1}, {-1, 2}, {2, 2}};
+        for (auto &o : off) {
+            const int64_t xx = x0 + o[0], yy = y0 + o[1];
+            if (!inside(l + 1, xx, yy)) continue;
+            if (internal.count(key_of(l + 1, xx, yy))) return true;
+        }
+        return false;
+    }
+};
+
+}  // namespace
+
+int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
+{
+    if (!c) return GF_E_INVALID;
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    const int64_t nw = (int64_t)c->desc.size();
+    const int8_t *flags = flags_in ? flags_in : (c->last_flags.size() == (size_t)nw ? c->last_flags.data() : nullptr);
+    if (!flags) return fail(c, GF_E_STATE, "no flags: call gf_tag first");
+    rc = fold_accumulators(c);
+    if (rc) return rc;
+    const int m = c->m;
+    std::vector<XferTaskH> xfer;
+    std::vector<int32_t> freed;
+    int64_t off = 0, total = 0;
+    for (size_t si = 0; si < c->sc.size(); ++si) {
+        Scen &s = c->sc[si];
+        const int64_t n = (int64_t)s.leaves.size();
+        const int8_t *fl = flags + off;
+        off += n;
+        std::vector<char> ref((size_t)n, 0), coa((size_t)n, 0);
+        for (int64_t k = 0; k < n; ++k) ref[(size_t)k] = fl[k] > 0 && s.leaves[(size_t)k].level < s.d.max_level;
+        // 2:1 face+corner balance closure of the refinement
+        Topo T{c, &s, {}};
+        for (int64_t k = 0; k < n; ++k) {
+            const Leaf &L = s.leaves[(size_t)k];
+            if (ref[(size_t)k]) { T.internal.insert(key_of(L.level, L.PI, L.PJ)); }
+            T.add_ancestors(L.level, L.PI, L.PJ);
+        }
+        for (bool changed = true; changed;) {
+            changed = false;
+            for (int64_t k = 0; k < n; ++k) {
+                const Leaf &L = s.leaves[(size_t)k];
+                if (ref[(size_t)k]) continue;
+                if (T.finer_than_next(L.level, L.PI, L.PJ)) {
+                    if (L.level >= s.d.max_level) return fail(c, GF_E_INVALID, "balance needs a level beyond max_level");
+                    ref[(size_t)k] = 1;
+                    T.internal.insert(key_of(L.level, L.PI, L.PJ));
+                    changed = true;
+                }
+            }
+        }
+        // coarsening of complete families whose parent stays balanced
+        for (int64_t k = 0; k < n; ++k) {
+            const Leaf &L = s.leaves[(size_t)k];
+            if (fl[k] >= 0 || ref[(size_t)k] || L.level <= s.d.min_level || (L.PI & 1) || (L.PJ & 1)) continue;
+            int sib[4];
+            bool ok = true;
+            for (int q = 0; q < 4 && ok; ++q) {
+                auto it = s.map.find(key_of(L.level, L.PI + (q & 1), L.PJ + (q >> 1)));
+                if (it == s.map.end()) { ok = false; break; }
+                sib[q] = it->second;
+                if (fl[sib[q]] >= 0 || ref[(size_t)sib[q]]) ok = false;
+            }
+            if (!ok) continue;
+            if (T.finer_than_next(L.level - 1, L.PI >> 1, L.PJ >> 1)) continue;
+            for (int q = 0; q < 4; ++q) coa[(size_t)sib[q]] = 1;
+        }
+        // new leaves; slots for children and parents are fresh
+        std::vector<Leaf> nl;
+        std::vector<Leaf *> fresh;
+        nl.reserve((size_t)n + 3 * (size_t)n);
+        int64_t need = 0;
+        for (int64_t k = 0; k < n; ++k) need += ref[(size_t)k] ? 4 : 0;
+        for (int64_t k = 0; k < n; ++k) need += (coa[(size_t)k] && !(s.leaves[(size_t)k].PI & 1) && !(s.leaves[(size_t)k].PJ & 1)) ? 1 : 0;
+        if (need > (int64_t)c->free_slots.size()) return fail(c, GF_E_NOMEM, "patch pool too small for the regrid");
+        struct Pending { int kind; int64_t src; int q; };
+        std::vector<Pending> pend;
+        for (int64_t k = 0; k < n; ++k) {
+            const Leaf &L = s.leaves[(size_t)k];
+            if (ref[(size_t)k]) {
+                for (int q = 0; q < 4; ++q) {
+                    Leaf C{L.level + 1, 2 * L.PI + (q & 1), 2 * L.PJ + (q >> 1), take_slot(c)};
+                    nl.push_back(C);
+                    pend.push_back({0, k, q});
+                }
+                freed.push_back(L.slot);
+            } else if (coa[(size_t)k]) {
+                if (!(L.PI & 1) && !(L.PJ & 1)) {
+                    Leaf P{L.level - 1, L.PI >> 1, L.PJ >> 1, take_slot(c)};
+                    nl.push_back(P);
+                    pend.push_back({1, k, 0});
+                }
+                freed.push_back(L.slot);
+            } else {
+                nl.push_back(L);
+                pend.push_back({2, k, 0});
+            }
+        }
+        std::vector<Leaf> old = s.leaves;
+        auto oldmap = s.map;
+        // transfer tasks (read the old slots, write the fresh ones)
+        for (size_t j = 0; j < nl.size(); ++j) {
+            const Pending &p = pend[j];
+            if (p.kind == 2) continue;
+            fresh.push_back(&nl[j]);
+            XferTaskH t{};
+            t.dst = nl[j].slot;
+            t.scen = (int32_t)si;
+            if (p.kind == 0) {
+                t.kind = 0; t.qx = p.q & 1; t.qy = p.q >> 1; t.src[0] = old[(size_t)p.src].slot;
+            } else {
+                t.kind = 1;
+                const Leaf &L = old[(size_t)p.src];
+                for (int q = 0; q < 4; ++q) t.src[q] = old[(size_t)oldmap[key_of(L.level, L.PI + (q & 1), L.PJ + (q >> 1))]].slot;
+            }
+            xfer.push_back(t);
+        }
+        rc = upload_bathy(c, s, fresh);
+        if (rc) return rc;
+        s.leaves = nl;
+        sort_leaves(c, s);
+        total += (int64_t)s.leaves.size();
+    }
+    if (!xfer.empty()) {
+        if ((int64_t)xfer.size() > c->xfer_cap) {
+            if (c->d_xfer) (void)hipFree(c->d_xfer);
+            c->xfer_cap = std::max<int64_t>((int64_t)xfer.size(), 1024);
+            HIPCHK(c, hipMalloc(&c->d_xfer, sizeof(XferTaskH) * (size_t)c->xfer_cap));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->d_xfer, xfer.data(), sizeof(XferTaskH) * xfer.size(), hipMemcpyHostToDevice, c->stream));
+        hipError_t e;
+        if (c->prec == GF_FP32)
+            e = gf_launch_transfer_f32(c->d_xfer, (int)xfer.size(), c->d_scen, (float *)c->q[0], (float *)c->q[1],
+                                       (const float *)c->b, c->cap, c->cfg.dry_tol, m, c->stream);
+        else
+            e = gf_launch_transfer_f64(c->d_xfer, (int)xfer.size(), c->d_scen, (double *)c->q[0], (double *)c->q[1],
+                                       (const double *)c->b, c->cap, c->cfg.dry_tol, m, c->stream);
+        if (e != hipSuccess) return fail(c, GF_E_HIP, "transfer launch: %s", hipGetErrorString(e));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    for (int32_t sl : freed) give_slot(c, sl);
+    c->topo_dirty = true;
+    rc = ensure_work(c);
+    if (rc) return rc;
+    if (n_leaves) *n_leaves = total;
+    return GF_OK;
+}
+
+int gf_mass(gf_ctx *c, int32_t scen, double *mass, double *clamp_volume, double *boundary_volume)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    rc = ensure_work(c);
+    if (rc) return rc;
+    const int nw = (int)c->desc.size();
+    hipError_t e;
+    if (c->prec == GF_FP32)
+        e = gf_launch_mass_f32(c->d_desc, nw, c->d_scen, (const float *)c->q[0], (const float *)c->q[1], c->cap, c->d_mass, c->m, c->stream);
+    else
+        e = gf_launch_mass_f64(c->d_desc, nw, c->d_scen, (const double *)c->q[0], (const double *)c->q[1], c->cap, c->d_mass, c->m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "mass launch: %s", hipGetErrorString(e));
+    std::vector<double> part((size_t)nw), ca((size_t)c->cap), ba((size_t)c->cap);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->d_mass, sizeof(double) * (size_t)nw, hipMemcpyDeviceToHost, c->stream));
+    const int cur = c->hs[(size_t)scen].cur;
+    HIPCHK(c, hipMemcpyAsync(ca.data(), c->cacc[cur], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ba.data(), c->bacc[cur], sizeof(double) * ba.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double S = 0.0, C = 0.0, cl = c->sc[(size_t)scen].clamp_base, bd = c->sc[(size_t)scen].bnd_base;
+    for (int k = 0; k < nw; ++k) {
+        if (c->desc[(size_t)k].scen != scen) continue;
+        const double v = part[(size_t)k], t = S + v;
+        if (std::fabs(S) >= std::fabs(v)) C += (S - t) + v; else C += (v - t) + S;
+        S = t;
+        cl += ca[(size_t)c->desc[(size_t)k].slot];
+        bd += ba[(size_t)c->desc[(size_t)k].slot];
+    }
+    if (mass) *mass = S + C;
+    if (clamp_volume) *clamp_volume = cl;
+    if (boundary_volume) *boundary_volume = bd;
+    return GF_OK;
+}
+
+int gf_time(gf_ctx *c, int32_t scen, double *t, double *dt_next, int64_t *steps, int64_t *rejected)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    const ScenDev &h = c->hs[(size_t)scen];
+    if (t) *t = h.t;
+    if (dt_next) *dt_next = h.dt;
+    if (steps) *steps = h.steps;
+    if (rejected) *rejected = h.rejected;
+    return GF_OK;
+}
+
+int gf_set_time(gf_ctx *c, int32_t scen, double t, double dt_next)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    c->hs[(size_t)scen].t = t;
+    c->hs[(size_t)scen].dt = dt_next;
+    return push_scen(c);
+}
+
+int gf_profile_enable(gf_ctx *c, int32_t on)
+{
+    if (!c) return GF_E_INVALID;
+    if (on && !c->prof) { c->prof_launches = 0; c->prof_ms = 0.0; }
+    c->prof = on != 0;
+    return GF_OK;
+}
+
+int gf_profile_read(gf_ctx *c, int64_t *launches, double *ms_total)
+{
+    if (!c) return GF_E_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double ms = 0.0;
+    for (int64_t k = 0; k < c->prof_launches; ++k) {
+        float x = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&x, c->ev[(size_t)(2 * k)], c->ev[(size_t)(2 * k + 1)]));
+        ms += x;
+    }
+    if (launches) *launches = c->prof_launches;
+    if (ms_total) *ms_total = ms;
+    c->prof_launches = 0;
+    return GF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal layout shared by the host core (gf_host.cpp) and the kernels
+// (gf_kernels.inc, built once per precision).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gf {
+
+// Halo regions of a patch (2-cell ghost layer), each fed by one source:
+//   0,1 west face (lower, upper half)   2,3 east face
+//   4,5 south face (left, right half)   6,7 north face
+//   8 SW corner  9 SE corner  10 NW corner  11 NE corner
+enum HaloKind : int32_t { HK_SAME = 0, HK_COARSE = 1, HK_FINE = 2, HK_PHYS = 3 };
+
+struct HaloSrc {
+    int32_t kind;   // HaloKind
+    int32_t slot;   // source patch slot (unused for HK_PHYS)
+    int32_t oi, oj; // index offsets, see the kernel's gather
+};
+
+// Per leaf work item.  Indices are global at the leaf's level.
+struct PatchDesc {
+    int32_t slot;
+    int32_t scen;
+    int32_t level;
+    int32_t phys;        // bit s set: side s (0 xlo,1 xhi,2 ylo,3 yhi) is a physical boundary
+    int32_t PI, PJ;      // global patch index
+    int32_t bc[4];       // boundary type per side (valid where phys bit set)
+    int32_t cf_face[4];  // reflux register index of a face touching a different level, or -1
+    int32_t cf_role[4];  // 0 none, 1 this patch is the coarse side, 2 the fine side
+    double dx, dy;
+    double xlo, ylo;     // lower-left corner of the patch
+    HaloSrc src[12];
+};
+
+// Reflux task: one coarse face next to two finer patches.
+struct RefluxTask {
+    int32_t slot;        // coarse patch slot
+    int32_t scen;
+    int32_t face;        // coarse face 0..3
+    int32_t reg_c;       // register of the coarse side (m entries)
+    int32_t reg_f[2];    // registers of the two fine faces (m entries each)
+    int32_t half_f[2];   // which coarse half each fine face covers (0 lower/left, 1 upper/right)
+    double area;         // coarse cell area
+};
+
+// Per-scenario clock and controller state, device resident.
+struct ScenDev {
+    double t, dt, t_end;
+    double dt_used;          // step length of the last attempt
+    double nu_last;
+    double manning_n;
+    double inflow_lo, inflow_hi;
+    double hydro_t[16], hydro_q[16];
+    int32_t n_hydro;
+    int32_t inflow_side;
+    int32_t cur;             // buffer index holding the current state
+    int32_t status;          // 0 ok, else a GF_E_* code
+    int64_t steps, rejected, target;
+    int32_t accepted_last;   // 1 if the last launch accepted a step
+    int32_t nan_flag;
+    unsigned long long smax_bits;  // max |s|/dx of the running attempt (double bits)
+};
+
+template <typename R>
+struct StepArgs {
+    const PatchDesc *desc;
+    int32_t n_work;
+    ScenDev *scen;
+    int32_t n_scen;
+    R *q0, *q1;              // [3][cap][m*m] per buffer
+    const R *b;              // [cap][m*m]
+    const R *bg;             // [cap][ring]
+    double *clamp_acc0, *clamp_acc1;   // [cap] per buffer
+    double *bnd_acc0, *bnd_acc1;       // [cap] per buffer
+    R *reg;                  // reflux registers [n_reg][m][3]
+    int64_t cap;             // pool capacity (slots)
+    double dt_fixed;         // >= 0: use this step length in every scenario
+    int32_t mode;            // 0 step, 1 speed-only pass
+    double g, cfl_desired, cfl_max;
+    R tau;                   // dry iff h <= tau (tau rounded down to R)
+    double tau64;
+    unsigned int *done_counter;
+    R *ghost_out;            // gf_fill_ghosts: [cap][4][(m+4)^2], else null
+};
+
+struct RefluxArgsBase {
+    const RefluxTask *tasks;
+    int32_t n_tasks;
+    ScenDev *scen;
+    int64_t cap;
+    double tau64;
+};
+
+}  // namespace gf
+
+// Launchers, one set per precision (defined in gf_kernels_f32.hip / _f64.hip).
+#define GF_DECL_LAUNCHERS(SFX, R)                                                                  \
+    hipError_t gf_launch_step_##SFX(const gf::StepArgs<R> &a, int m, hipStream_t s);               \
+    hipError_t gf_launch_reflux_##SFX(const gf::RefluxArgsBase &a, R *q0, R *q1, const R *reg,     \
+                                      double *ca0, double *ca1, int m, hipStream_t s);             \
+    hipError_t gf_launch_tag_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,         \
+                                   const R *q0, const R *q1, const R *b, int64_t cap,              \
+                                   const double *thr, const int32_t *lev_limits, double tau64,     \
+                                   int8_t *flags, int m, hipStream_t s);                           \
+    hipError_t gf_launch_mass_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,        \
+                                    const R *q0, const R *q1, int64_t cap, double *out, int m,     \
+                                    hipStream_t s);                                                 \
+    hipError_t gf_launch_transfer_##SFX(const void *tasks, int n, const gf::ScenDev *scen, R *q0, R *q1, \
+                                        const R *b, int64_t cap, double tau, int m, hipStream_t s);
+
+// regrid transfer task (layout shared with the kernels)
+namespace gf {
+struct XferTaskH {
+    int32_t kind, dst, scen, qx, qy, src[4];
+};
+}
+
+GF_DECL_LAUNCHERS(f32, float)
+GF_DECL_LAUNCHERS(f64, double)

@@ -49,3 +49,16 @@ def to_finest(sc, leaves, st, field, level):
         blk = np.kron(st[k, field], np.ones((r, r)))
         out[PJ * m * r:(PJ + 1) * m * r, PI * m * r:(PI + 1) * m * r] = blk
     return out
+
+
+def init_oracle(o, sc, precision="f64"):
+    """Initial state from the scenario recipe on every oracle leaf, formed from
+    the oracle's own bathymetry."""
+    from paper_2403_15435_amd.inputs import initial_state
+    lv = o.leaves()
+    for k in range(lv.shape[0]):
+        b = o.get_field(k, 3)
+        h, hu, hv = initial_state(sc, lv[k], b, precision)
+        o.set_field(k, 0, np.asarray(h, dtype=np.float64))
+        o.set_field(k, 1, np.asarray(hu, dtype=np.float64))
+        o.set_field(k, 2, np.asarray(hv, dtype=np.float64))

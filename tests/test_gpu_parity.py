@@ -1,0 +1,329 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+FP64 path: per-cell relative error in h <= 1e-12 where the oracle has
+h >= 1e-2 m; hu, hv within 1e-12 of their max norm; the step lengths are the
+oracle's own.  FP32 path (split h / b, FP64 wet/dry decisions) against the
+FP64 oracle started from the same FP32 initial state on the FP32-rounded bed:
+|dh|/h <= 2e-5 away from fronts, |dh| <= 1e-3 m at front cells (cells with a
+cell of depth <= 1e-2 m within their 5x5 neighbourhood).  Integer work
+(leaves, flags) and the bathymetry are compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2403_15435_amd as gf
+from paper_2403_15435_amd import inputs
+from helpers import assemble, init_oracle, to_finest
+
+pytestmark = pytest.mark.gpu
+
+TAU = 1e-4
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def gpu_init_like(ctx, o, precision):
+    """Give the library the oracle's initial state (FP32: rounded)."""
+    st = o.state()
+    if precision == "f32":
+        st = st.astype(np.float32).astype(np.float64)
+    ctx.set_state(0, st)
+
+
+def check_fp64(g, o, what=""):
+    """g, o: (n, 4, m, m) states of the library and the oracle."""
+    hg, ho = g[:, 0], o[:, 0]
+    flips = np.count_nonzero((hg > TAU) != (ho > TAU))
+    assert flips == 0, f"{what}: {flips} cells changed wet/dry state"
+    mask = ho >= 1e-2
+    if mask.any():
+        rel = np.abs(hg - ho)[mask] / ho[mask]
+        assert rel.max() <= 1e-12, f"{what}: h rel err {rel.max():.3e}"
+    for f in (1, 2):
+        scale = max(np.abs(o[:, f]).max(), 1e-300)
+        err = np.abs(g[:, f] - o[:, f]).max()
+        assert err <= 1e-12 * scale, f"{what}: field {f} err {err:.3e} (scale {scale:.3e})"
+
+
+def check_fp32(sc, leaves, g, o, level):
+    Ho = assemble(sc, leaves, o, 0, level)
+    Hg = assemble(sc, leaves, g, 0, level)
+    shallow = (Ho <= 1e-2) | (Hg <= 1e-2)
+    pad = np.pad(shallow, 2, mode="edge")
+    near = np.zeros_like(shallow)
+    for dj in range(5):
+        for di in range(5):
+            near |= pad[dj:dj + shallow.shape[0], di:di + shallow.shape[1]]
+    away = ~near
+    rel = np.abs(Hg - Ho)[away] / Ho[away] if away.any() else np.zeros(1)
+    front = np.abs(Hg - Ho)[near] if near.any() else np.zeros(1)
+    return float(rel.max()), float(front.max())
+
+
+def amr_mesh_16():
+    """Levels 1..3 on one tree of 16^2 patches, 2:1 balanced across faces and
+    corners: quadrants (0,0) and (1,1) at level 1, (1,0) at level 2, (0,1) at
+    level 2 with its top-left patch at level 3."""
+    lv = [(0, 1, 0, 0), (0, 1, 1, 1)]
+    lv += [(0, 2, 2 + a, b) for b in range(2) for a in range(2)]
+    lv += [(0, 2, 0, 2), (0, 2, 1, 2), (0, 2, 1, 3)]
+    lv += [(0, 3, a, 6 + b) for b in range(2) for a in range(2)]
+    return np.array(lv, np.int32)
+
+
+# --------------------------------------------------------------- bathymetry
+def test_bathymetry_bit_exact(orc):
+    """Cell bathymetry of an AMR mesh spanning levels below and above the
+    terrain level equals the oracle's bit for bit (FP64) and its rounding (FP32)."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=5, dem_level=2)
+    sc.min_level, sc.max_level = 0, 4
+    leaves = amr_mesh_16()
+    o = orc.Oracle(sc, leaves=leaves)
+    for prec in (gf.GF_FP64, gf.GF_FP32):
+        ctx = gf.Context([sc], precision=prec, max_patches=64)
+        ctx.set_leaves(0, leaves)
+        assert np.array_equal(ctx.leaves(0), o.leaves())
+        bg = ctx.state(0)[:, 3]
+        bo = o.state()[:, 3]
+        if prec == gf.GF_FP64:
+            assert np.array_equal(bg, bo)
+        else:
+            assert np.array_equal(bg, bo.astype(np.float32).astype(np.float64))
+
+
+# --------------------------------------------------------------- ghost fill
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_ghost_fill_matches_oracle(orc, prec):
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+    sc.min_level, sc.max_level = 1, 3
+    sc.bc = (0, 1, 0, 1)   # walls low, extrapolation high
+    leaves = amr_mesh_16()
+    o = orc.Oracle(sc, leaves=leaves)
+    if prec == gf.GF_FP32:
+        o.set_bathy_f32(True)
+    init_oracle(o, sc)
+    # give the water some motion so that momenta are exercised
+    st = o.state()
+    st[:, 1] = 0.3 * st[:, 0]
+    st[:, 2] = -0.2 * st[:, 0]
+    if prec == gf.GF_FP32:
+        st = st.astype(np.float32).astype(np.float64)
+    o.set_state(st)
+    ctx = gf.Context([sc], precision=prec, max_patches=64)
+    ctx.set_leaves(0, leaves)
+    ctx.set_state(0, st)
+    o.fill_ghosts()
+    ctx.fill_ghosts()
+    worst = 0.0
+    for k in range(len(leaves)):
+        for f in range(4):
+            a = ctx.ghosted(0, k, f)
+            b = o.get_ghosted(k, f)
+            if prec == gf.GF_FP64:
+                assert np.array_equal(a, b), (k, f, np.abs(a - b).max())
+            else:
+                worst = max(worst, np.abs(a - b).max() / (np.abs(b).max() + 1e-30))
+    if prec == gf.GF_FP32:
+        assert worst <= 1e-6
+
+
+# ------------------------------------------------------ uniform FP64 parity
+def test_ritter_fp64_parity(orc):
+    """The whole dry-bed dam break to t = 50 s on the oracle's step lengths."""
+    sc = inputs.ritter_dambreak(128, 16)
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+    gpu_init_like(ctx, o, "f64")
+    nu, dts = o.advance(10000, return_dt=True)
+    assert o.t == 50.0
+    ctx.step(len(dts), dts)
+    check_fp64(ctx.state(0), o.state(), "ritter")
+    t, _, steps, _ = ctx.time(0)
+    assert steps == len(dts) and t == pytest.approx(50.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("m,level", [(16, 3), (32, 2)])
+def test_reservoir_fp64_parity(orc, m, level):
+    """Fractal terrain, circular reservoir, friction, walls: 100 steps."""
+    sc = inputs.reservoir_fractal(level=level, m=m, L=2000.0, seed=2, radius=300.0)
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+    gpu_init_like(ctx, o, "f64")
+    nu, dts = o.advance(100, return_dt=True)
+    ctx.step(len(dts), dts)
+    check_fp64(ctx.state(0), o.state(), f"reservoir m{m}")
+
+
+def test_adaptive_step_controller(orc):
+    """Library-chosen step lengths follow the same controller: first step from
+    the speed pass, then dt cfl/nu, truncated at t_end."""
+    sc = inputs.ritter_dambreak(128, 16)
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+    gpu_init_like(ctx, o, "f64")
+    o.advance(10000)
+    st = ctx.step(10000)
+    t, dt, steps, rej = ctx.time(0)
+    assert t == 50.0
+    assert steps == o.steps and rej == o.rejected
+    check_fp64(ctx.state(0), o.state(), "adaptive ritter")
+
+
+# --------------------------------------------------------------- FP32 path
+@pytest.mark.parametrize("nsteps", [1, 10, 100])
+def test_reservoir_fp32_vs_oracle(orc, nsteps):
+    sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
+    o = orc.Oracle(sc)
+    o.set_bathy_f32(True)
+    init_oracle(o, sc, "f32")
+    ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=128)
+    gpu_init_like(ctx, o, "f32")
+    nu, dts = o.advance(nsteps, return_dt=True)
+    ctx.step(len(dts), dts)
+    rel, front = check_fp32(sc, o.leaves(), ctx.state(0), o.state(), 3)
+    print(f"fp32 {nsteps} steps: rel away from fronts {rel:.3e}, front abs {front:.3e}")
+    assert rel <= 2e-5
+    assert front <= 1e-3
+
+
+# -------------------------------------------------------------------- AMR
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_amr_step_parity_and_mass(orc, prec):
+    """Mixed-level mesh with coarse/fine faces: ghosts, update and refluxing."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+    sc.min_level, sc.max_level = 1, 3
+    leaves = amr_mesh_16()
+    o = orc.Oracle(sc, leaves=leaves)
+    if prec == gf.GF_FP32:
+        o.set_bathy_f32(True)
+    init_oracle(o, sc, "f32" if prec == gf.GF_FP32 else "f64")
+    ctx = gf.Context([sc], precision=prec, max_patches=64)
+    ctx.set_leaves(0, leaves)
+    gpu_init_like(ctx, o, "f32" if prec == gf.GF_FP32 else "f64")
+    m0 = o.mass()[0]
+    nu, dts = o.advance(40, return_dt=True)
+    ctx.step(len(dts), dts)
+    g, r = ctx.state(0), o.state()
+    if prec == gf.GF_FP64:
+        check_fp64(g, r, "amr")
+        M, cl, bd = ctx.mass(0)
+        assert abs(M - m0 - cl - bd) <= 1e-12 * m0
+    else:
+        Hg = to_finest(sc, leaves, g, 0, 3)
+        Ho = to_finest(sc, leaves, r, 0, 3)
+        wet = Ho > 1e-2
+        assert (np.abs(Hg - Ho)[wet] / Ho[wet]).max() <= 1e-4
+        M, cl, bd = ctx.mass(0)
+        assert abs(M - m0 - cl - bd) <= 1e-6 * m0
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_tag_and_regrid_bit_exact(orc, prec):
+    """Flags, the balanced new mesh and the moved data agree with the oracle."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=4, radius=400.0)
+    sc.min_level, sc.max_level = 1, 4
+    o = orc.Oracle(sc)
+    if prec == gf.GF_FP32:
+        o.set_bathy_f32(True)
+    init_oracle(o, sc, "f32" if prec == gf.GF_FP32 else "f64")
+    ctx = gf.Context([sc], precision=prec, max_patches=400)
+    gpu_init_like(ctx, o, "f32" if prec == gf.GF_FP32 else "f64")
+    m0 = ctx.mass(0)[0]
+    for cycle in range(3):
+        fo = o.tag()
+        fg = ctx.tag()
+        assert np.array_equal(fo, fg), cycle
+        no = o.regrid(fo)
+        ng = ctx.regrid(fg)
+        assert no == ng
+        assert np.array_equal(o.leaves(), ctx.leaves(0))
+        g, r = ctx.state(0), o.state()
+        if prec == gf.GF_FP64:
+            check_fp64(g, r, f"regrid {cycle}")
+            assert np.array_equal(g[:, 3], r[:, 3])
+        else:
+            assert np.array_equal(g[:, 3], r[:, 3])
+        nu, dts = o.advance(4, return_dt=True)
+        ctx.step(len(dts), dts)
+        if prec == gf.GF_FP32:
+            # keep the two in lock step: the FP32 data decides the next flags
+            o.set_state(ctx.state(0))
+    assert len(set(ctx.leaves(0)[:, 1])) >= 2
+    M, cl, bd = ctx.mass(0)
+    tol = 1e-12 if prec == gf.GF_FP64 else 1e-6
+    assert abs(M - m0 - cl - bd) <= tol * m0
+
+
+# ------------------------------------------------------------ invariants
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_lake_at_rest_bit_exact(orc, prec):
+    """Still water over fractal terrain with dry islands stays exactly at rest."""
+    sc = inputs.lake_at_rest(level=3, m=16, eta0=110.0, seed=7)
+    ctx = gf.Context([sc], precision=prec, max_patches=64)
+    s0 = ctx.set_initial(0)
+    assert (s0[:, 0] == 0).any() and (s0[:, 0] > 0).any()
+    ctx.step(300)
+    assert np.array_equal(ctx.state(0), s0)
+
+
+def test_fp32_mass_conservation_large(orc):
+    """A 512^2 reservoir run for 400 steps conserves mass to 1e-6 in FP32."""
+    sc = inputs.reservoir_fractal(level=4, m=32, L=5000.0, seed=2, radius=400.0)
+    ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=256)
+    ctx.set_initial(0)
+    m0 = ctx.mass(0)[0]
+    ctx.step(400)
+    M, cl, bd = ctx.mass(0)
+    assert abs(M - m0 - cl - bd) <= 1e-6 * m0
+    assert bd == 0.0
+
+
+# ------------------------------------------------------------ error paths
+def test_fixed_step_above_cfl_is_refused(orc):
+    sc = inputs.ritter_dambreak(128, 16)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+    ctx.set_initial(0)
+    s0 = ctx.state(0)
+    with pytest.raises(gf.GFError) as e:
+        ctx.step(1, [10.0])
+    assert e.value.code == gf.GF_E_CFL
+    assert np.array_equal(ctx.state(0), s0)
+
+
+def test_non_finite_state_is_reported(orc):
+    sc = inputs.ritter_dambreak(128, 16)
+    ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=64)
+    st = ctx.set_initial(0)
+    h = st[5, 0].copy()
+    h[3, 3] = np.nan
+    ctx.set_patch(0, 5, 0, h)
+    with pytest.raises(gf.GFError) as e:
+        ctx.step(1, [0.01])
+    assert e.value.code == gf.GF_E_NUMERIC
+
+
+def test_calls_out_of_order(orc):
+    sc = inputs.ritter_dambreak(128, 16)
+    dem = sc.dem
+    sc.dem = None
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+    with pytest.raises(gf.GFError) as e:
+        ctx.step(1)
+    assert e.value.code == gf.GF_E_STATE
+    with pytest.raises(gf.GFError) as e:
+        ctx.set_leaves(0, sc.uniform_leaves(3))
+    assert e.value.code == gf.GF_E_STATE
+    ctx.set_bathymetry(0, dem, 0)
+    with pytest.raises(gf.GFError) as e:
+        ctx.set_leaves(0, np.array([[0, 3, 0, 0]], np.int32))
+    assert e.value.code == gf.GF_E_INVALID

@@ -8,14 +8,14 @@ import pytest
 
 from paper_2403_15435_amd import inputs
 from exact_swe import ritter, sample
-from helpers import assemble, row_scenario
+from helpers import assemble, init_oracle, row_scenario
 
 G = 9.81
 
 
 def run_uniform(oracle_mod, sc, nsteps=100000, leaves=None):
     o = oracle_mod.Oracle(sc, leaves=leaves)
-    o.set_initial()
+    init_oracle(o, o.sc)
     o.advance(nsteps)
     return o
 
@@ -105,8 +105,8 @@ def test_axis_exchange_symmetry(oracle_mod):
     sct = inputs.reservoir_fractal(level=2, m=16, radius=250.0, L=2000.0, seed=9)
     sct.dem = np.ascontiguousarray(sc.dem.T)
     sct.eta_fn = (lambda X, Y, b: np.where(np.hypot(Y - 700.0, X - 1100.0) <= 250.0, b + 20.0, -1e9))
-    a = oracle_mod.Oracle(sc); a.set_initial()
-    b = oracle_mod.Oracle(sct); b.set_initial()
+    a = oracle_mod.Oracle(sc); init_oracle(a, a.sc)
+    b = oracle_mod.Oracle(sct); init_oracle(b, b.sc)
     dts = [0.05 * (1 + 0.1 * k) for k in range(30)]
     a.advance(30, dts)
     b.advance(30, dts)
@@ -122,7 +122,7 @@ def test_axis_exchange_symmetry(oracle_mod):
 def test_lake_at_rest_bit_exact_with_dry_islands(oracle_mod):
     sc = inputs.lake_at_rest(level=3, m=16, eta0=110.0, seed=7)
     o = oracle_mod.Oracle(sc)
-    o.set_initial()
+    init_oracle(o, o.sc)
     s0 = o.state()
     assert (s0[:, 0] == 0).any() and (s0[:, 0] > 0).any()
     o.advance(200)
@@ -140,7 +140,7 @@ def test_lake_at_rest_amr_wet_faces(oracle_mod):
     fl[12:16] = -1
     o.regrid(fl)
     assert len(set(o.leaves()[:, 1])) >= 2
-    o.set_initial()
+    init_oracle(o, o.sc)
     o.advance(100)
     st = o.state()
     assert np.abs(st[:, 1:3]).max() <= 1e-10
@@ -151,7 +151,7 @@ def test_mass_conservation_uniform_and_amr(oracle_mod):
     sc = inputs.reservoir_fractal(level=3, m=16, radius=300.0, L=2000.0, seed=2)
     sc.min_level, sc.max_level = 2, 4
     o = oracle_mod.Oracle(sc)
-    o.set_initial()
+    init_oracle(o, o.sc)
     m0 = o.mass()[0]
     o.advance(8)
     for cycle in range(6):
@@ -175,7 +175,7 @@ def test_friction_matches_ode_solution(oracle_mod):
     sc.eta_fn = lambda X, Y, b: h0 + 0.0 * X
     sc.uv_fn = lambda X, Y, h: (h * u0, h * v0)
     o = oracle_mod.Oracle(sc)
-    o.set_initial()
+    init_oracle(o, o.sc)
     dts = [0.3] * 50
     o.advance(50, dts)
     st = o.state()
@@ -325,7 +325,7 @@ def test_refine_then_coarsen_roundtrip(oracle_mod):
     sc.eta_fn = lambda X, Y, b: np.maximum(b + 0.5, 126.0) + 0.001 * X
     sc.uv_fn = lambda X, Y, h: (0.1 * h * np.sin(X / 50), 0.2 * h * np.cos(Y / 70))
     o = oracle_mod.Oracle(sc)
-    o.set_initial()
+    init_oracle(o, o.sc)
     s0 = o.state()
     o.regrid(np.array([1, 0, 0, 0], np.int8))
     assert o.n_leaves == 7
