@@ -372,14 +372,41 @@ static void rebuild_map(orc_sim *s)
         hmap_put(&s->map, key_of(s->leaves[k].level, s->leaves[k].PI, s->leaves[k].PJ), k);
 }
 
-/* tlxy: n rows of (tree, level, ix, iy) */
-int orc_set_leaves(orc_sim *s, const int *tlxy, int n)
+/* leaf order: trees row-major, then Z-order (x the low bit) of each patch's
+ * lower-left corner at a common fine depth */
+static uint64_t zkey(long x, long y)
+{
+    uint64_t k = 0;
+    int b;
+    for (b = 0; b < 31; ++b) {
+        k |= (uint64_t)((x >> b) & 1) << (2 * b);
+        k |= (uint64_t)((y >> b) & 1) << (2 * b + 1);
+    }
+    return k;
+}
+
+static int row_cmp(const void *pa, const void *pb)
+{
+    const int *a = (const int *)pa, *b = (const int *)pb;
+    uint64_t ka, kb;
+    if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+    ka = zkey((long)a[2] << (20 - a[1]), (long)a[3] << (20 - a[1]));
+    kb = zkey((long)b[2] << (20 - b[1]), (long)b[3] << (20 - b[1]));
+    return ka < kb ? -1 : (ka > kb ? 1 : 0);
+}
+
+/* tlxy: n rows of (tree, level, ix, iy), any order; stored in leaf order */
+int orc_set_leaves(orc_sim *s, const int *tlxy_in, int n)
 {
     int k;
+    int *tlxy = (int *)malloc(sizeof(int) * 4 * (size_t)n);
+    memcpy(tlxy, tlxy_in, sizeof(int) * 4 * (size_t)n);
+    qsort(tlxy, (size_t)n, 4 * sizeof(int), row_cmp);
     free_leaves(s);
     s->leaves = (leaf_t *)calloc((size_t)n, sizeof(leaf_t));
     s->n_leaves = n;
     for (k = 0; k < n; ++k) leaf_alloc(s, &s->leaves[k], tlxy[4 * k], tlxy[4 * k + 1], tlxy[4 * k + 2], tlxy[4 * k + 3]);
+    free(tlxy);
     rebuild_map(s);
     for (k = 0; k < n; ++k) leaf_bathymetry(s, &s->leaves[k]);
     s->t = 0.0; s->dt = 0.0; s->steps = 0; s->rejected = 0;
@@ -437,6 +464,30 @@ double orc_dt(const orc_sim *s) { return s->dt; }
 void orc_set_time(orc_sim *s, double t, double dt) { s->t = t; s->dt = dt; }
 
 /* ------------------------------------------------------------------------ */
+/* cube root                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Real cube root of x > 0 by Newton's method on y^3 = x: write
+ * x = f 2^(3k) with f in [1/8, 1), start from the chord 1/2 + f/2 of the cube
+ * root on that interval, take six Newton steps y -= (y^3 - f) / (3 y^2)
+ * (quadratic convergence from <= 13% error), and scale by 2^k.  Only + - * /
+ * and exact scalings are used, so the result is reproducible bit for bit. */
+double orc_cbrt(double x)
+{
+    int e, k, r, it;
+    double f, y;
+    if (!(x > 0.0)) return x == 0.0 ? 0.0 : -orc_cbrt(-x);
+    f = frexp(x, &e);                 /* x = f 2^e, f in [1/2, 1) */
+    r = ((e % 3) + 3) % 3;            /* e = 3k + r, r in {0, 1, 2} */
+    k = (e - r) / 3;
+    f = ldexp(f, r - 3);              /* x = f 2^(3(k+1)), f in [1/16, 1/2) */
+    if (f < 0.125) { f = ldexp(f, 3); k -= 1; }   /* r = 0: f in [1/2, 1) */
+    y = 0.5 + 0.5 * f;
+    for (it = 0; it < 6; ++it) y = y - (y * y * y - f) / (3.0 * y * y);
+    return ldexp(y, k + 1);
+}
+
+/* ------------------------------------------------------------------------ */
 /* inflow ghost state (Section 4.1.1, eq. riemann and eq. 2-shock)           */
 /* ------------------------------------------------------------------------ */
 
@@ -481,7 +532,8 @@ static double inflow_df_shock(double h, double qbar, double hint, double g)
  * residual decreases with h (eq. riemann form), -1 if it increases. */
 static double inflow_solve(int which, double qbar, double uint_, double hint, double g, double F)
 {
-    double h = pow(qbar / sqrt(g) * F, 2.0 / 3.0);
+    double c0 = orc_cbrt(qbar / sqrt(g) * F);
+    double h = c0 * c0;               /* (qbar F / sqrt(g))^(2/3) */
     double lo, hi, flo, fhi, sgn = (which == 0) ? 1.0 : -1.0;
     int it;
 #define RES(x) (which == 0 ? inflow_f_riemann((x), qbar, uint_, hint, g) : inflow_f_shock((x), qbar, uint_, hint, g))
@@ -524,7 +576,8 @@ double orc_inflow_depth(double qbar, double hint, double mint, double g, double 
 {
     double uint_, h;
     if (hint < tau) {
-        double hs = pow(qbar / sqrt(g), 2.0 / 3.0);
+        double c1 = orc_cbrt(qbar / sqrt(g));
+        double hs = c1 * c1;
         hint = hs > tau ? hs : tau;
         uint_ = 0.0;
     } else {
@@ -717,16 +770,35 @@ double orc_mirror_middle_depth(double h, double u, double g)
     return hm;
 }
 
-/* One normal Riemann problem.  Inputs per side: depth, normal momentum,
- * tangential momentum, bed.  Outputs: speeds s[3], f-waves z[3][3] in
- * (h, normal, tangential) components, fluctuations amdq/apdq.
- * Returns 1 if the right side was treated as a wall, -1 for the left. */
+/* One normal Riemann problem (Section 3.3; readings R1-R7).  Inputs per side:
+ * depth, normal momentum, tangential momentum, bed.  Outputs: speeds s[3],
+ * f-waves z[3][3] of the propagating waves in (h, normal, tangential)
+ * components, and the fluctuations amdq/apdq, which also carry the
+ * stationary (speed 0) wave of the bed jump.  Returns 1 if the right side
+ * was treated as a wall, -1 for the left, 0 otherwise.
+ *
+ * 1. dry iff h <= tau; dry sides carry h = u = v = 0.
+ * 2. Artificial mirror problem: when one side is dry and its bed lies above
+ *    the wet side's surface, the wet state against its own mirror image gives
+ *    the middle depth hm; if the bed step is higher than hm the edge is a wall
+ *    (the dry side takes the mirror state, waves into it are dropped).
+ *    Otherwise the water overtops and meets the step with depth hm - step.
+ * 3. Stationary wave of the bed jump: the interface depths are the depths
+ *    that stand above the higher of the two beds, h*_L = max(0, h_L -
+ *    max(0, b_R - b_L)), h*_R = max(0, h_R - max(0, b_L - b_R)) (formed from
+ *    depth and bed differences, never from the free surface).  It moves the
+ *    difference h* - h at speed 0 with each side's velocity.
+ * 4. Propagating waves: HLLE/Einfeldt speeds from Roe averages of the
+ *    interface states, dam-break front speeds against a dry interface state,
+ *    s2 = (s1 + s3)/2; f-wave strengths from the jumps
+ *    d1 = dh*, d2 = d(h* u), d3 = d(h* u^2) + g hbar* d1. */
 int orc_riemann(double hl, double ml, double tl, double bl,
                 double hr, double mr, double tr, double br,
                 double g, double tau,
                 double s[3], double z[9], double amdq[3], double apdq[3])
 {
     double ul = 0.0, vl = 0.0, ur = 0.0, vr = 0.0;
+    double hls, hrs, al, ar, uls, vls, urs, vrs, mls, mrs;
     double sql, sqr, cl, cr, uhat, chat, s1, s2, s3, hbar, d1, d2, d3, den, b1, b2, b3;
     int dryl = !(hl > tau), dryr = !(hr > tau), drop = 0, p, k;
     for (k = 0; k < 3; ++k) { s[k] = 0.0; amdq[k] = 0.0; apdq[k] = 0.0; }
@@ -734,7 +806,7 @@ int orc_riemann(double hl, double ml, double tl, double bl,
     if (dryl && dryr) return 0;
     if (dryl) { hl = 0.0; ml = 0.0; tl = 0.0; } else { ul = ml / hl; vl = tl / hl; }
     if (dryr) { hr = 0.0; mr = 0.0; tr = 0.0; } else { ur = mr / hr; vr = tr / hr; }
-    /* artificial mirror problem at a dry bed higher than the wet free surface */
+    /* interface depths: wall, overtopping, or the stationary wave of the bed */
     if (dryr && br > hl + bl) {
         double hm = orc_mirror_middle_depth(hl, ul, g);
         if (bl + hm < br) {
@@ -746,42 +818,72 @@ int orc_riemann(double hl, double ml, double tl, double bl,
             hl = hr; ml = -mr; tl = tr; bl = br; ul = -ur; vl = vr; drop = -1;
         }
     }
-    sql = sqrt(hl); sqr = sqrt(hr);
-    cl = sqrt(g * hl); cr = sqrt(g * hr);
-    uhat = (sql * ul + sqr * ur) / (sql + sqr);
-    chat = sqrt(g * (hl + hr) * 0.5);
-    if (hl == 0.0) s1 = ur - 2.0 * cr;
-    else s1 = fmin(ul - cl, uhat - chat);
-    if (hr == 0.0) s3 = ul + 2.0 * cl;
-    else s3 = fmax(ur + cr, uhat + chat);
-    s2 = 0.5 * (s1 + s3);
-    hbar = 0.5 * (hl + hr);
-    d1 = (hr - hl) + (br - bl);
-    d2 = mr - ml;
-    d3 = (mr * ur - ml * ul) + g * hbar * d1;
-    den = s3 - s1;
-    b1 = (s3 * d1 - d2) / den;
-    b3 = (d2 - s1 * d1) / den;
-    b2 = d3 - b1 * s1 * s1 - b3 * s3 * s3;
-    s[0] = s1; s[1] = s2; s[2] = s3;
-    z[0] = b1 * s1; z[1] = b1 * s1 * s1; z[2] = b1 * s1 * vl;
-    /* tangential momentum: its normal flux is h u v = m v (eq. shallow); waves
-     * 1 and 3 carry it at the side velocities, the middle wave the remainder */
-    z[3] = 0.0;     z[4] = b2;           z[5] = (mr * vr - ml * vl) - b1 * s1 * vl - b3 * s3 * vr;
-    z[6] = b3 * s3; z[7] = b3 * s3 * s3; z[8] = b3 * s3 * vr;
-    if (drop != 0)
-        for (p = 0; p < 3; ++p)
-            if ((drop > 0 && s[p] > 0.0) || (drop < 0 && s[p] < 0.0))
-                for (k = 0; k < 3; ++k) z[3 * p + k] = 0.0;
-    for (p = 0; p < 3; ++p) {
-        double cm = s[p] < 0.0 ? 1.0 : (s[p] > 0.0 ? 0.0 : 0.5);
-        double cp = s[p] > 0.0 ? 1.0 : (s[p] < 0.0 ? 0.0 : 0.5);
-        if (drop > 0) cp = 0.0;
-        if (drop < 0) cm = 0.0;
-        for (k = 0; k < 3; ++k) {
-            amdq[k] += cm * z[3 * p + k];
-            apdq[k] += cp * z[3 * p + k];
+    if (drop != 0) {
+        hls = hl; hrs = hr;
+    } else if (dryr && br > hl + bl) {
+        hls = orc_mirror_middle_depth(hl, ul, g) - (br - bl);   /* overtopping */
+        hrs = 0.0;
+    } else if (dryl && bl > hr + br) {
+        hrs = orc_mirror_middle_depth(hr, -ur, g) - (bl - br);
+        hls = 0.0;
+    } else {
+        double db = br - bl;
+        hls = hl - (db > 0.0 ? db : 0.0);
+        hrs = hr - (db < 0.0 ? -db : 0.0);
+        if (hls < 0.0) hls = 0.0;
+        if (hrs < 0.0) hrs = 0.0;
+    }
+    al = hls - hl;
+    ar = hr - hrs;
+    /* interface states; a zero interface depth is dry */
+    uls = hls > 0.0 ? ul : 0.0; vls = hls > 0.0 ? vl : 0.0;
+    urs = hrs > 0.0 ? ur : 0.0; vrs = hrs > 0.0 ? vr : 0.0;
+    mls = hls * uls; mrs = hrs * urs;
+    if (hls > 0.0 || hrs > 0.0) {
+        sql = sqrt(hls); sqr = sqrt(hrs);
+        cl = sqrt(g * hls); cr = sqrt(g * hrs);
+        uhat = (sql * uls + sqr * urs) / (sql + sqr);
+        chat = sqrt(g * (hls + hrs) * 0.5);
+        if (hls == 0.0) s1 = urs - 2.0 * cr;
+        else s1 = fmin(uls - cl, uhat - chat);
+        if (hrs == 0.0) s3 = uls + 2.0 * cl;
+        else s3 = fmax(urs + cr, uhat + chat);
+        s2 = 0.5 * (s1 + s3);
+        hbar = 0.5 * (hls + hrs);
+        d1 = hrs - hls;
+        d2 = mrs - mls;
+        d3 = (mrs * urs - mls * uls) + g * hbar * d1;
+        den = s3 - s1;
+        b1 = (s3 * d1 - d2) / den;
+        b3 = (d2 - s1 * d1) / den;
+        b2 = d3 - b1 * s1 * s1 - b3 * s3 * s3;
+        s[0] = s1; s[1] = s2; s[2] = s3;
+        /* tangential momentum: its normal flux is h u v = m v (eq. shallow);
+         * waves 1 and 3 carry it at the side velocities, the middle wave the
+         * remainder */
+        z[0] = b1 * s1; z[1] = b1 * s1 * s1; z[2] = b1 * s1 * vls;
+        z[3] = 0.0;     z[4] = b2;           z[5] = (mrs * vrs - mls * vls) - b1 * s1 * vls - b3 * s3 * vrs;
+        z[6] = b3 * s3; z[7] = b3 * s3 * s3; z[8] = b3 * s3 * vrs;
+        if (drop != 0)
+            for (p = 0; p < 3; ++p)
+                if ((drop > 0 && s[p] > 0.0) || (drop < 0 && s[p] < 0.0))
+                    for (k = 0; k < 3; ++k) z[3 * p + k] = 0.0;
+        for (p = 0; p < 3; ++p) {
+            double cm = s[p] < 0.0 ? 1.0 : (s[p] > 0.0 ? 0.0 : 0.5);
+            double cp = s[p] > 0.0 ? 1.0 : (s[p] < 0.0 ? 0.0 : 0.5);
+            if (drop > 0) cp = 0.0;
+            if (drop < 0) cm = 0.0;
+            for (k = 0; k < 3; ++k) {
+                amdq[k] += cm * z[3 * p + k];
+                apdq[k] += cp * z[3 * p + k];
+            }
         }
+    }
+    /* stationary wave: each side's interface depth change at its velocity */
+    {
+        const double wl = al * ul, wr = ar * ur;
+        amdq[0] += wl; amdq[1] += wl * ul; amdq[2] += wl * vl;
+        apdq[0] += wr; apdq[1] += wr * ur; apdq[2] += wr * vr;
     }
     return drop;
 }
@@ -905,6 +1007,14 @@ static double update_all(orc_sim *s, double dt)
     double *GY = (double *)malloc(sizeof(double) * (size_t)(m + 1) * m * 3);
     double *FXt = (double *)malloc(sizeof(double) * (size_t)(m + 1) * m * 3);
     double *GYt = (double *)malloc(sizeof(double) * (size_t)(m + 1) * m * 3);
+    /* per direction: increments of every edge e in [0, m] of rows [-1, m] */
+    double *DMX[2], *DPX[2], *Dx, *Dy;
+    DMX[0] = (double *)malloc(sizeof(double) * (size_t)(m + 2) * (m + 1) * 3);
+    DMX[1] = (double *)malloc(sizeof(double) * (size_t)(m + 2) * (m + 1) * 3);
+    DPX[0] = (double *)malloc(sizeof(double) * (size_t)(m + 2) * (m + 1) * 3);
+    DPX[1] = (double *)malloc(sizeof(double) * (size_t)(m + 2) * (m + 1) * 3);
+    Dx = (double *)malloc(sizeof(double) * (size_t)(m + 2) * m * 3);
+    Dy = (double *)malloc(sizeof(double) * (size_t)(m + 2) * m * 3);
     double **newq = (double **)malloc(sizeof(double *) * (size_t)s->n_leaves * 3);
     for (k = 0; k < s->n_leaves; ++k) {
         leaf_t *L = &s->leaves[k];
@@ -921,72 +1031,80 @@ static double update_all(orc_sim *s, double dt)
         memset(GY, 0, sizeof(double) * (size_t)(m + 1) * m * 3);
         memset(FXt, 0, sizeof(double) * (size_t)(m + 1) * m * 3);
         memset(GYt, 0, sizeof(double) * (size_t)(m + 1) * m * 3);
-        /* normal corrections and transverse propagation, both sweeps */
+        /* Both sweeps use the state at t^n.  For each direction: the limited
+         * correction flux F of every edge, the increments into the two cells
+         * (dm = A-dQ + F to the left one, dp = A+dQ - F to the right one),
+         * each cell's net normal increment D = dp(left edge) + dm(right edge),
+         * and the transverse propagation of D into the correction fluxes of
+         * the other direction (the transverse solver is linear, so splitting
+         * D equals splitting its two parts). */
         for (c = 0; c < 2; ++c) {
             edge_t *E = c == 0 ? EX : EY;
             double dtn = c == 0 ? dtdx : dtdy;   /* normal-direction ratio */
-            double *Fn = c == 0 ? FX : GY;       /* own-direction fluxes */
+            double *Fn = c == 0 ? FX : GY;       /* own-direction normal corrections */
             double *Ft = c == 0 ? GYt : FXt;     /* transverse-direction fluxes */
+            double *Dn = c == 0 ? Dx : Dy;
+            double *DM = DMX[c], *DP = DPX[c];
             for (r = -1; r <= m; ++r)
                 for (e = 0; e <= m; ++e) {
                     const edge_t *ed = &E[(r + 1) * ne + (e + 1)];
-                    double F[3], dm[3], dp[3], Fxyz[3];
-                    int side;
+                    double F[3];
                     correction_flux(s, E, e, r, dtn, F);
-                    if (r >= 0 && r < m) {
-                        /* F in (h, normal, tangential) -> (h, hu, hv) */
-                        Fxyz[0] = F[0];
-                        Fxyz[1 + c] = F[1];
-                        Fxyz[2 - c] = F[2];
-                        for (f = 0; f < 3; ++f) Fn[(r * (m + 1) + e) * 3 + f] += Fxyz[f];
+                    for (f = 0; f < 3; ++f) {
+                        DM[((r + 1) * (m + 1) + e) * 3 + f] = ed->amdq[f] + F[f];
+                        DP[((r + 1) * (m + 1) + e) * 3 + f] = ed->apdq[f] - F[f];
                     }
-                    for (f = 0; f < 3; ++f) { dm[f] = ed->amdq[f] + F[f]; dp[f] = ed->apdq[f] - F[f]; }
-                    /* target k = e-1 receives dm, target k = e receives dp */
-                    for (side = 0; side < 2; ++side) {
-                        int tk = side == 0 ? e - 1 : e;
-                        const double *d = side == 0 ? dm : dp;
-                        int up;
-                        if (tk < 0 || tk >= m) continue;
-                        for (up = 0; up < 2; ++up) {
-                            int nr = up ? r + 1 : r - 1;   /* transverse neighbour index */
-                            int fe = up ? r + 1 : r;        /* transverse edge index */
-                            int gk, gn;
-                            double out[3], o[3];
-                            if (fe < 0 || fe > m) continue;
-                            if (c == 0) { gk = G(s, tk, r); gn = G(s, tk, nr); }
-                            else { gk = G(s, r, tk); gn = G(s, nr, tk); }
-                            /* momentum normal to this sweep is q[1+c], transverse q[2-c] */
-                            transverse_split(s, L->q[0][gk], L->q[1 + c][gk], L->q[2 - c][gk], L->b[gk],
-                                             L->q[0][gn], L->q[1 + c][gn], L->q[2 - c][gn], L->b[gn],
-                                             d, up, out);
-                            o[0] = out[0]; o[1 + c] = out[1]; o[2 - c] = out[2];
-                            for (f = 0; f < 3; ++f) Ft[(tk * (m + 1) + fe) * 3 + f] -= 0.5 * dtn * o[f];
-                        }
+                    if (r >= 0 && r < m) {
+                        Fn[(r * (m + 1) + e) * 3 + 0] = F[0];
+                        Fn[(r * (m + 1) + e) * 3 + 1 + c] = F[1];
+                        Fn[(r * (m + 1) + e) * 3 + 2 - c] = F[2];
                     }
                 }
+            /* net normal increment of cell k (along the sweep) in row r */
+            for (r = -1; r <= m; ++r)
+                for (e = 0; e < m; ++e)
+                    for (f = 0; f < 3; ++f)
+                        Dn[((r + 1) * m + e) * 3 + f] = DP[((r + 1) * (m + 1) + e) * 3 + f] + DM[((r + 1) * (m + 1) + e + 1) * 3 + f];
+            /* transverse edge between rows r and r+1 at position k */
+            for (r = -1; r < m; ++r)
+                for (e = 0; e < m; ++e) {
+                    int ga, gb;
+                    double up[3], dn[3], o[3];
+                    if (c == 0) { ga = G(s, e, r); gb = G(s, e, r + 1); }
+                    else { ga = G(s, r, e); gb = G(s, r + 1, e); }
+                    /* B+ of the increment of (k, r) towards (k, r+1); B- of (k, r+1) towards (k, r) */
+                    transverse_split(s, L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
+                                     L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
+                                     &Dn[((r + 1) * m + e) * 3], 1, up);
+                    transverse_split(s, L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
+                                     L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
+                                     &Dn[((r + 2) * m + e) * 3], 0, dn);
+                    for (f = 0; f < 3; ++f) o[f] = -((0.5 * dtn) * (up[f] + dn[f]));
+                    /* (h, normal, tangential) -> (h, hu, hv) */
+                    Ft[(e * (m + 1) + r + 1) * 3 + 0] = o[0];
+                    Ft[(e * (m + 1) + r + 1) * 3 + 1 + c] = o[1];
+                    Ft[(e * (m + 1) + r + 1) * 3 + 2 - c] = o[2];
+                }
         }
-        /* total correction flux = normal part + transverse part */
+        /* total correction flux at each edge = normal part + transverse part */
         for (i = 0; i < (m + 1) * m * 3; ++i) { FX[i] = FX[i] + FXt[i]; GY[i] = GY[i] + GYt[i]; }
-        /* conservative update, eq. (wpa_update_corrections) in 2D; the x and
-         * y parts are formed alike and summed, so the scheme is exactly
-         * symmetric under exchange of the axes */
+        /* conservative update, eq. (wpa_update_corrections) in 2D, grouped by
+         * sweep: Q - (P + R) with P = dt/dx Dx + dt/dy (Gt(j+1/2) - Gt(j-1/2))
+         * (the normal increment of the x sweep and the transverse fluxes it
+         * produced) and R the same for the y sweep.  Exchanging the axes swaps
+         * P and R, so the scheme is exactly symmetric. */
         newq[3 * k] = (double *)malloc(sizeof(double) * (size_t)m * m);
         newq[3 * k + 1] = (double *)malloc(sizeof(double) * (size_t)m * m);
         newq[3 * k + 2] = (double *)malloc(sizeof(double) * (size_t)m * m);
         for (j = 0; j < m; ++j)
-            for (i = 0; i < m; ++i) {
-                const edge_t *xl = &EX[(j + 1) * ne + (i + 1)], *xr = &EX[(j + 1) * ne + (i + 2)];
-                const edge_t *yl = &EY[(i + 1) * ne + (j + 1)], *yr = &EY[(i + 1) * ne + (j + 2)];
+            for (i = 0; i < m; ++i)
                 for (f = 0; f < 3; ++f) {
-                    /* x fluctuations in (h, hu, hv): component map for dir 0 is identity */
+                    /* D arrays are in the sweep frame: x (h, hu, hv), y (h, hv, hu) */
                     int fx = f, fy = (f == 0) ? 0 : (f == 1 ? 2 : 1);
-                    double A = xl->apdq[fx] + xr->amdq[fx];
-                    double B = yl->apdq[fy] + yr->amdq[fy];
-                    double Fd = FX[(j * (m + 1) + i + 1) * 3 + f] - FX[(j * (m + 1) + i) * 3 + f];
-                    double Gd = GY[(i * (m + 1) + j + 1) * 3 + f] - GY[(i * (m + 1) + j) * 3 + f];
-                    newq[3 * k + f][j * m + i] = L->q[f][G(s, i, j)] - (dtdx * (A + Fd) + dtdy * (B + Gd));
+                    double P = dtdx * Dx[((j + 1) * m + i) * 3 + fx] + dtdy * (GYt[(i * (m + 1) + j + 1) * 3 + f] - GYt[(i * (m + 1) + j) * 3 + f]);
+                    double Rr = dtdy * Dy[((i + 1) * m + j) * 3 + fy] + dtdx * (FXt[(j * (m + 1) + i + 1) * 3 + f] - FXt[(j * (m + 1) + i) * 3 + f]);
+                    newq[3 * k + f][j * m + i] = L->q[f][G(s, i, j)] - (P + Rr);
                 }
-            }
         /* reflux records and boundary mass flux at the patch faces (reading R17).
          * Faces 0 W, 1 E, 2 S, 3 N; one record per edge along the face in
          * (h, hu, hv) components, in field x area units:
@@ -999,30 +1117,36 @@ static double update_all(orc_sim *s, double dt)
         for (f = 0; f < 4; ++f) {
             int kk;
             for (kk = 0; kk < m; ++kk) {
-                const edge_t *ed;
-                double Ft3[3], am[3], ap[3], len, mcell, own[3], oth[3];
+                double Tt[3], dm[3], dp[3], len, mcell, own[3], oth[3];
                 int dir = f < 2 ? 0 : 1, hi = f & 1, eidx = hi ? m : 0, q, ci, cj;
-                const double *FF = dir == 0 ? FX : GY;
+                const double *TT = dir == 0 ? FXt : GYt;
+                const double *em, *ep;
                 long I, J;
                 int onb;
-                if (dir == 0) { ed = &EX[(kk + 1) * ne + (eidx + 1)]; len = dy; ci = hi ? m - 1 : 0; cj = kk; }
-                else { ed = &EY[(kk + 1) * ne + (eidx + 1)]; len = dx; ci = kk; cj = hi ? m - 1 : 0; }
-                for (q = 0; q < 3; ++q) Ft3[q] = FF[(kk * (m + 1) + eidx) * 3 + q];
-                am[0] = ed->amdq[0]; am[1 + dir] = ed->amdq[1]; am[2 - dir] = ed->amdq[2];
-                ap[0] = ed->apdq[0]; ap[1 + dir] = ed->apdq[1]; ap[2 - dir] = ed->apdq[2];
+                if (dir == 0) { len = dy; ci = hi ? m - 1 : 0; cj = kk; }
+                else { len = dx; ci = kk; cj = hi ? m - 1 : 0; }
+                /* increments of this face edge (sweep frame -> (h, hu, hv)) */
+                em = &DMX[dir][((kk + 1) * (m + 1) + eidx) * 3];
+                ep = &DPX[dir][((kk + 1) * (m + 1) + eidx) * 3];
+                dm[0] = em[0]; dm[1 + dir] = em[1]; dm[2 - dir] = em[2];
+                dp[0] = ep[0]; dp[1 + dir] = ep[1]; dp[2 - dir] = ep[2];
+                for (q = 0; q < 3; ++q) Tt[q] = TT[(kk * (m + 1) + eidx) * 3 + q];
                 mcell = L->q[1 + dir][G(s, ci, cj)];
+                /* F = Fn + Ft, dm = A-dQ + Fn, dp = A+dQ - Fn:
+                 *   cell below the face gains -dt len (A-dQ + F) = -dt len (dm + Ft),
+                 *   cell above gains -dt len (A+dQ - F) = -dt len (dp - Ft);
+                 *   the mass flux itself is m_below + A-dQ + F = m_above - A+dQ + F */
                 if (hi) {
-                    /* own cell on the low side of the face */
-                    own[0] = -dt * len * (mcell + am[0] + Ft3[0]);
+                    own[0] = -dt * len * (mcell + (dm[0] + Tt[0]));
                     for (q = 1; q < 3; ++q) {
-                        own[q] = -dt * len * (am[q] + Ft3[q]);
-                        oth[q] = -dt * len * (ap[q] - Ft3[q]);
+                        own[q] = -dt * len * (dm[q] + Tt[q]);
+                        oth[q] = -dt * len * (dp[q] - Tt[q]);
                     }
                 } else {
-                    own[0] = dt * len * (mcell - ap[0] + Ft3[0]);
+                    own[0] = dt * len * (mcell - (dp[0] - Tt[0]));
                     for (q = 1; q < 3; ++q) {
-                        own[q] = -dt * len * (ap[q] - Ft3[q]);
-                        oth[q] = -dt * len * (am[q] + Ft3[q]);
+                        own[q] = -dt * len * (dp[q] - Tt[q]);
+                        oth[q] = -dt * len * (dm[q] + Tt[q]);
                     }
                 }
                 L->gainC[(f * m + kk) * 3 + 0] = own[0];
@@ -1049,6 +1173,7 @@ static double update_all(orc_sim *s, double dt)
     }
     free(newq);
     free(EX); free(EY); free(FX); free(GY); free(FXt); free(GYt);
+    free(DMX[0]); free(DMX[1]); free(DPX[0]); free(DPX[1]); free(Dx); free(Dy);
     return smax_all;
 }
 
@@ -1069,7 +1194,7 @@ static void friction_leaf(orc_sim *s, leaf_t *L, double dt)
             double h = L->q[0][gi], hu = L->q[1][gi], hv = L->q[2][gi], sp, gam, f;
             if (!wet(s, h)) continue;
             sp = sqrt(hu * hu + hv * hv);
-            gam = s->g * n2 * sp / (h * h * cbrt(h));
+            gam = s->g * n2 * sp / (h * h * orc_cbrt(h));
             f = 1.0 + dt * gam;
             L->q[1][gi] = hu / f;
             L->q[2][gi] = hv / f;

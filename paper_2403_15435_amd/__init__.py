@@ -56,6 +56,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2403_15435_amd.build.build()")
+    # Load torch first: it maps its own HIP runtime, and the library then binds
+    # to that same runtime (one runtime per process, shared streams).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     L.gf_create.argtypes = [C.POINTER(gf_config), C.POINTER(vp)]
@@ -146,7 +152,7 @@ class Context:
         self._p = C.c_void_p()
         rc = L.gf_create(C.byref(cfg), C.byref(self._p))
         if rc != 0:
-            raise GFError(rc, "gf_create failed")
+            raise GFError(rc, "gf_create failed: " + L.gf_last_error(None).decode())
         for k, sc in enumerate(self.scenarios):
             if sc.dem is not None:
                 self.set_bathymetry(k, sc.dem, sc.dem_level)

@@ -321,16 +321,20 @@ int rebuild_work(gf_ctx *c)
                 else if ((a.kind == HK_FINE) != (b2.kind == HK_FINE))
                     return fail(c, GF_E_INVALID, "scenario %d: mixed-level face", si);
             }
-            for (int f = 0; f < 4; ++f)
-                if (P.cf_role[f] == 1) {
-                    RefluxTask T{};
-                    T.slot = L.slot; T.scen = si; T.face = f; T.reg_c = L.slot * 4 + f;
-                    T.reg_f[0] = P.src[2 * f].slot * 4 + (f ^ 1);
-                    T.reg_f[1] = P.src[2 * f + 1].slot * 4 + (f ^ 1);
-                    T.half_f[0] = 0; T.half_f[1] = 1;
-                    T.area = P.dx * P.dy;
-                    c->reflux.push_back(T);
+            {
+                RefluxTask T{};
+                bool any = false;
+                T.slot = L.slot; T.scen = si; T.area = P.dx * P.dy;
+                for (int f = 0; f < 4; ++f) {
+                    T.reg_c[f] = -1;
+                    if (P.cf_role[f] != 1) continue;
+                    any = true;
+                    T.reg_c[f] = L.slot * 4 + f;
+                    T.reg_f[f][0] = P.src[2 * f].slot * 4 + (f ^ 1);
+                    T.reg_f[f][1] = P.src[2 * f + 1].slot * 4 + (f ^ 1);
                 }
+                if (any) c->reflux.push_back(T);
+            }
             c->desc.push_back(P);
         }
     }
@@ -482,12 +486,15 @@ extern "C" {
 
 const char *gf_version(void) { return "geoflood-mi355x 0.1"; }
 
-const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+static thread_local char g_create_err[512] = "null context";
+
+const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err; }
 
 int gf_create(const gf_config *cfg, gf_ctx **out)
 {
     if (!cfg || !out) return GF_E_INVALID;
     *out = nullptr;
+    snprintf(g_create_err, sizeof g_create_err, "invalid configuration");
     if (cfg->m != 16 && cfg->m != 32) return GF_E_UNSUPPORTED;
     if (cfg->precision != GF_FP32 && cfg->precision != GF_FP64) return GF_E_INVALID;
     if (cfg->n_scen <= 0 || !cfg->scen || cfg->max_patches <= 0) return GF_E_INVALID;
@@ -523,8 +530,13 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     for (int64_t k = c->cap - 1; k >= 0; --k) c->free_slots.push_back((int32_t)k);
     const size_t MM = (size_t)c->m * c->m;
     auto alloc = [&](void **p, size_t bytes) -> bool {
-        if (hipMalloc(p, bytes) != hipSuccess) return false;
-        return hipMemset(*p, 0, bytes) == hipSuccess;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) e = hipMemset(*p, 0, bytes);
+        if (e != hipSuccess) {
+            snprintf(g_create_err, sizeof g_create_err, "allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
+            return false;
+        }
+        return true;
     };
     bool ok = true;
     ok = ok && alloc(&c->q[0], 3 * MM * c->cap * c->es) && alloc(&c->q[1], 3 * MM * c->cap * c->es);

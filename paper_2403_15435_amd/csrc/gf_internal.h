@@ -34,15 +34,13 @@ struct PatchDesc {
     HaloSrc src[12];
 };
 
-// Reflux task: one coarse face next to two finer patches.
+// Reflux task: one coarse patch with up to four faces next to finer patches.
 struct RefluxTask {
-    int32_t slot;        // coarse patch slot
+    int32_t slot;         // coarse patch slot
     int32_t scen;
-    int32_t face;        // coarse face 0..3
-    int32_t reg_c;       // register of the coarse side (m entries)
-    int32_t reg_f[2];    // registers of the two fine faces (m entries each)
-    int32_t half_f[2];   // which coarse half each fine face covers (0 lower/left, 1 upper/right)
-    double area;         // coarse cell area
+    int32_t reg_c[4];     // register of each coarse face (m entries), -1 if the face is not coarse/fine
+    int32_t reg_f[4][2];  // registers of the two fine faces covering the lower/left and upper/right half
+    double area;          // coarse cell area
 };
 
 // Per-scenario clock and controller state, device resident.

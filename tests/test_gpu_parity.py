@@ -39,6 +39,9 @@ def gpu_init_like(ctx, o, precision):
 
 def check_fp64(g, o, what=""):
     """g, o: (n, 4, m, m) states of the library and the oracle."""
+    same = np.array_equal(g[:, :3], o[:, :3])
+    d = np.abs(g[:, :3] - o[:, :3]).max()
+    print(f"{what}: bit-identical {same}, max abs diff {d:.3e}", flush=True)
     hg, ho = g[:, 0], o[:, 0]
     flips = np.count_nonzero((hg > TAU) != (ho > TAU))
     assert flips == 0, f"{what}: {flips} cells changed wet/dry state"
@@ -53,8 +56,11 @@ def check_fp64(g, o, what=""):
 
 
 def check_fp32(sc, leaves, g, o, level):
-    Ho = assemble(sc, leaves, o, 0, level)
-    Hg = assemble(sc, leaves, g, 0, level)
+    """Max relative h error away from fronts and max absolute error at front
+    cells (a cell of depth <= 1e-2 m in either solution within the 5x5
+    neighbourhood), on the mesh projected to `level`."""
+    Ho = to_finest(sc, leaves, o, 0, level)
+    Hg = to_finest(sc, leaves, g, 0, level)
     shallow = (Ho <= 1e-2) | (Hg <= 1e-2)
     pad = np.pad(shallow, 2, mode="edge")
     near = np.zeros_like(shallow)
@@ -180,30 +186,59 @@ def test_adaptive_step_controller(orc):
 
 
 # --------------------------------------------------------------- FP32 path
-@pytest.mark.parametrize("nsteps", [1, 10, 100])
-def test_reservoir_fp32_vs_oracle(orc, nsteps):
-    sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
-    o = orc.Oracle(sc)
+def smooth_bed(sc, amp=10.0):
+    L = sc.x1 - sc.x0
+    xs = np.linspace(0.0, L, sc.dem.shape[1])
+    sc.dem = np.ascontiguousarray(100.0 + amp * np.sin(2 * np.pi * xs[None, :] / L) * np.cos(2 * np.pi * xs[:, None] / L))
+    return sc
+
+
+FP32_CASES = {
+    # Manning friction on the rough bed amplifies round-off by ~1.3 per step
+    # (pinned in test_roundoff_amplification): judged at short horizons
+    "fractal_friction": (lambda: inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0), (1, 10)),
+    # no amplification on the rough bed without friction
+    "fractal_frictionless": (lambda: inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0,
+                                                               manning_n=0.0), (100, 500)),
+    # smooth bed with friction, up to the time the thin return flow at the
+    # centre (exactly symmetric in the oracle) becomes unstable
+    "smooth_friction": (lambda: smooth_bed(inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)),
+                        (100, 300)),
+}
+
+
+@pytest.mark.parametrize("case", list(FP32_CASES))
+def test_fp32_vs_fp64_oracle(orc, case):
+    """The oracle picks steps at Courant number 0.7 so that the FP32 run, whose
+    fastest thin-film front cells differ slightly, stays below 1."""
+    mk, horizons = FP32_CASES[case]
+    sc = mk()
+    o = orc.Oracle(sc, cfl_desired=0.7)
     o.set_bathy_f32(True)
     init_oracle(o, sc, "f32")
     ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=128)
     gpu_init_like(ctx, o, "f32")
-    nu, dts = o.advance(nsteps, return_dt=True)
-    ctx.step(len(dts), dts)
-    rel, front = check_fp32(sc, o.leaves(), ctx.state(0), o.state(), 3)
-    print(f"fp32 {nsteps} steps: rel away from fronts {rel:.3e}, front abs {front:.3e}")
-    assert rel <= 2e-5
-    assert front <= 1e-3
+    done = 0
+    for hz in horizons:
+        nu, dts = o.advance(hz - done, return_dt=True)
+        ctx.step(len(dts), dts)
+        done = hz
+        rel, front = check_fp32(sc, o.leaves(), ctx.state(0), o.state(), 3)
+        print(f"fp32 {case} {hz} steps: rel away from fronts {rel:.3e}, front abs {front:.3e}", flush=True)
+        assert rel <= 2e-5, (case, hz, rel)
+        assert front <= 1e-3, (case, hz, front)
 
 
 # -------------------------------------------------------------------- AMR
 @pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
 def test_amr_step_parity_and_mass(orc, prec):
-    """Mixed-level mesh with coarse/fine faces: ghosts, update and refluxing."""
-    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+    """Mixed-level mesh with coarse/fine faces: ghosts, update and refluxing.
+    (FP32: frictionless, so that round-off is not amplified.)"""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0,
+                                  manning_n=0.033 if prec == gf.GF_FP64 else 0.0)
     sc.min_level, sc.max_level = 1, 3
     leaves = amr_mesh_16()
-    o = orc.Oracle(sc, leaves=leaves)
+    o = orc.Oracle(sc, leaves=leaves, cfl_desired=0.9 if prec == gf.GF_FP64 else 0.7)
     if prec == gf.GF_FP32:
         o.set_bathy_f32(True)
     init_oracle(o, sc, "f32" if prec == gf.GF_FP32 else "f64")
@@ -219,10 +254,9 @@ def test_amr_step_parity_and_mass(orc, prec):
         M, cl, bd = ctx.mass(0)
         assert abs(M - m0 - cl - bd) <= 1e-12 * m0
     else:
-        Hg = to_finest(sc, leaves, g, 0, 3)
-        Ho = to_finest(sc, leaves, r, 0, 3)
-        wet = Ho > 1e-2
-        assert (np.abs(Hg - Ho)[wet] / Ho[wet]).max() <= 1e-4
+        rel, front = check_fp32(sc, leaves, g, r, 3)
+        print(f"fp32 amr 40 steps: rel away from fronts {rel:.3e}, front abs {front:.3e}", flush=True)
+        assert rel <= 2e-5 and front <= 1e-3
         M, cl, bd = ctx.mass(0)
         assert abs(M - m0 - cl - bd) <= 1e-6 * m0
 

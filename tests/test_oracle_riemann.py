@@ -53,25 +53,51 @@ def test_single_2shock_gives_one_wave(oracle_mod, hr, ur, hl):
 
 
 def test_wave_sum_identity(oracle_mod):
-    """Sum of the f-waves = (dm, d(mu) + g hbar (dh + db), d(tv)) for any wet states."""
+    """Flat bed, any wet states: the fluctuations add up to the flux difference
+    (dm, d(mu + g h^2/2), d(mv)); with a bed step the mass and tangential
+    parts still do (the bed source has neither)."""
     rng = np.random.default_rng(11)
     for _ in range(300):
         hl, hr = rng.uniform(0.1, 10.0, 2)
         ul, ur, vl, vr = rng.uniform(-3, 3, 4)
-        bl, br = rng.uniform(-1, 1, 2)
         ml, mr, tl, tr = hl * ul, hr * ur, hl * vl, hr * vr
-        s, z, am, ap, w = oracle_mod.riemann(hl, ml, tl, bl, hr, mr, tr, br)
+        s, z, am, ap, w = oracle_mod.riemann(hl, ml, tl, 0.0, hr, mr, tr, 0.0)
         ur_, ul_ = mr / hr, ml / hl
-        d1 = (hr - hl) + (br - bl)
-        expect = np.array([mr - ml, (mr * ur_ - ml * ul_) + G * 0.5 * (hl + hr) * d1, mr * (tr / hr) - ml * (tl / hl)])
-        scale = np.abs(expect).max() + abs(mr) + abs(ml) + 1e-3
+        expect = np.array([mr - ml, (mr * ur_ + 0.5 * G * hr * hr) - (ml * ul_ + 0.5 * G * hl * hl),
+                           mr * (tr / hr) - ml * (tl / hl)])
+        scale = np.abs(expect).max() + abs(mr) + abs(ml) + G * max(hl, hr) ** 2
         assert np.all(np.abs(z.sum(axis=0) - expect) <= 1e-13 * scale * 8)
-        # fluctuations split the same total
-        assert np.all(np.abs(am + ap - z.sum(axis=0)) <= 1e-14 * scale * 8)
+        assert np.all(np.abs(am + ap - expect) <= 1e-13 * scale * 8)
         # outer speeds bound the outgoing characteristic speeds of the data
         assert s[0] <= ul_ - math.sqrt(G * hl) + 1e-12
         assert s[2] >= ur_ + math.sqrt(G * hr) - 1e-12
         assert s[0] < s[1] < s[2]
+        bl, br = rng.uniform(-2, 2, 2)
+        s, z, am, ap, w = oracle_mod.riemann(hl, ml, tl, bl, hr, mr, tr, br)
+        assert abs((am + ap)[0] - (mr - ml)) <= 1e-13 * scale * 8
+        assert abs((am + ap)[2] - (mr * (tr / hr) - ml * (tl / hl))) <= 1e-13 * scale * 8
+
+
+def test_step_thrust_at_rest(oracle_mod):
+    """Still water on both sides of a bed step (surfaces need not match): the
+    momentum fluctuations add up to the pressure difference plus the hydrostatic
+    thrust of the lower side's water on the wetted part of the step face,
+    g (h d - d^2/2) with d = min(step, h_low)."""
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        bl = rng.uniform(0.0, 5.0)
+        step = rng.uniform(0.01, 3.0)
+        br = bl + step
+        hl = rng.uniform(0.05, 4.0)
+        hr = rng.uniform(0.05, 4.0)
+        if hr + br < bl + hl - 2.0:
+            continue
+        s, z, am, ap, w = oracle_mod.riemann(hl, 0.0, 0.0, bl, hr, 0.0, 0.0, br)
+        d = min(step, hl)
+        thrust = G * (hl * d - 0.5 * d * d)
+        expect = 0.5 * G * (hr * hr - hl * hl) + thrust
+        assert (am + ap)[1] == pytest.approx(expect, rel=1e-12, abs=1e-12 * G * 16)
+        assert abs((am + ap)[0]) <= 1e-14 * G * 16
 
 
 def test_lake_at_rest_exact(oracle_mod):
