@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 import numpy as np
 
 METRIC = "cell-updates/s and % HBM roofline, FP32-batched AMR vs FP64 plain, 1 MI355X"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_fp32_reservoir2048_hbm_traffic.txt")
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"f32": 28.0, "f64": 56.0}
 
@@ -30,10 +31,17 @@ def workload():
     return inputs.reservoir_fractal(level=6, m=32, L=10000.0, seed=2, radius=400.0, h_res=20.0, manning_n=0.033)
 
 
-def run_gpu(sc, precision, warmup, steps):
+def wet_workload():
+    from paper_2403_15435_amd import inputs
+    return inputs.wet_dambreak(level=6, m=32, L=10000.0, seed=2, radius=400.0, manning_n=0.033)
+
+
+def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False):
     import torch
     import paper_2403_15435_amd as gf
     ctx = gf.Context([sc], precision=precision, max_patches=4096)
+    if step_threads:
+        ctx.set_step_threads(step_threads)
     ctx.set_initial(0)
     ctx.step(warmup)
     torch.cuda.synchronize()
@@ -46,12 +54,16 @@ def run_gpu(sc, precision, warmup, steps):
     ctx.profile_enable(False)
     cells = int(st.cell_updates)
     mass = ctx.mass(0)
+    out = {"wall": wall, "cell_updates": cells, "steps": int(st.steps), "launches": launches,
+           "kernel_ms": ms, "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads()}
+    if wet_fraction:
+        h = ctx.state(0)[:, 0]
+        out["wet_cell_fraction"] = float(np.count_nonzero(h > 1e-4)) / h.size
     ctx.close()
-    return {"wall": wall, "cell_updates": cells, "steps": int(st.steps), "launches": launches,
-            "kernel_ms": ms, "rejected": int(st.rejected), "mass": mass.tolist()}
+    return out
 
 
-def cpu_baseline(sc, steps=8):
+def cpu_baseline(sc, steps=48):
     import oracle
     from paper_2403_15435_amd.inputs import initial_state
     oracle.build(force=False)
@@ -70,6 +82,42 @@ def cpu_baseline(sc, steps=8):
             "sample": f"{o.steps} adaptive steps of the full 2048^2 workload (FP64, one thread), {dt:.1f} s"}
 
 
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, scaled by the copy-kernel calibration; None
+    when the summary was taken on different kernel sources."""
+    from paper_2403_15435_amd.build import source_digest
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) * 1024.0
+
+
+def calibrate_copy(mib=512, reps=5):
+    """Device-to-device copy of a known size, run under the same HBM byte
+    counters as the step kernel to scale them: each copy reads and writes
+    `mib` MiB exactly once."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kib_read": mib * 1024, "copy_kib_written": mib * 1024, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,17 +125,45 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--step-threads", type=int, default=0, help="step-kernel workgroup size (0: library default)")
+    ap.add_argument("--wet-steps", type=int, default=200, help="steps of the all-wet comparison run (0: skip)")
+    ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
+                    help="run only one path (for counter collection); the JSON line needs both")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (for scaling HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
     import paper_2403_15435_amd as gf
     sc = workload()
     print(f"[bench] workload ready: {sc.name}, {4096} patches", file=sys.stderr, flush=True)
-    r32 = run_gpu(sc, gf.GF_FP32, args.warmup, args.steps)
+    nt = args.step_threads or None
+    if args.precision == "f64":
+        r64 = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.fp64_steps, nt)
+        print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
+        return
+    r32 = run_gpu(sc, gf.GF_FP32, args.warmup, args.steps, nt, wet_fraction=True)
     print(f"[bench] fp32 done: {r32}", file=sys.stderr, flush=True)
-    r64 = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.fp64_steps)
+    if args.precision == "f32":
+        return
+    r64 = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.fp64_steps, nt)
     print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
+    wet = None
+    if args.wet_steps > 0:
+        wsc = wet_workload()
+        w32 = run_gpu(wsc, gf.GF_FP32, 10, args.wet_steps, nt)
+        w64 = run_gpu(wsc, gf.GF_FP64, 10, max(args.wet_steps // 2, 1), nt)
+        print(f"[bench] all-wet fp32 {w32}\n[bench] all-wet fp64 {w64}", file=sys.stderr, flush=True)
+        wl = w32["kernel_ms"] / max(w32["launches"], 1) / 1e3
+        wet = {"workload": "same grid and terrain under a lake at 155 m (every cell wet), column at 165 m r=400 m",
+               "fp32_cell_updates_per_s": w32["cell_updates"] / w32["wall"],
+               "fp64_cell_updates_per_s": w64["cell_updates"] / w64["wall"],
+               "fp32_avg_launch_us": wl * 1e6,
+               "fp32_hbm_frac": BYTES_PER_UPDATE["f32"] * 4096 * 1024 / wl / 1e9 / HBM_PEAK_GBS}
     cups32 = r32["cell_updates"] / r32["wall"]
     cups64 = r64["cell_updates"] / r64["wall"]
     cells_per_launch = 4096 * 32 * 32
@@ -105,11 +181,16 @@ def main():
                                "reservoir h=20 m r=400 m, n=0.033, walls, adaptive CFL 0.9",
                    "patches": 4096, "cells": cells_per_launch},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (counters x copy calibration)",
+                     "algorithmic_bytes_per_launch": BYTES_PER_UPDATE["f32"] * cells_per_launch,
                      "kernel": "step_kernel<32,256> (fp32)", "avg_launch_us": avg_launch_s * 1e6},
         "fp64_plain": {"value": cups64, "unit": "cell-updates/s", "steps": r64["steps"],
                        "speedup_fp32_over_fp64": cups32 / cups64},
         "cpu_baseline": cpu,
+        "wet_cell_fraction_end": r32.get("wet_cell_fraction"),
+        "step_threads": r32.get("step_threads"),
+        "all_wet": wet,
     }
     print(json.dumps(line))
 

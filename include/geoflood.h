@@ -60,7 +60,7 @@ typedef struct {
     double manning_n;            /* eq. (manning); 0 disables friction */
     int32_t bc[4];               /* GF_BC_* per side */
     int32_t inflow_side;         /* side carrying the inflow segment, or -1 */
-    double inflow_lo, inflow_hi; /* segment along that side (Section 4.1.1) */
+    double inflow_lo, inflow_hi; /* segment along that side (Section 5.1.1) */
     const double *hydro;         /* n_hydro pairs (t [s], Q [m^3/s]), piecewise linear; copied */
     int32_t n_hydro;             /* <= 16 */
     double tag_h_refine;         /* depth refine threshold H_r [m] */
@@ -98,7 +98,7 @@ void gf_destroy(gf_ctx *ctx);
 /* Bathymetry of scenario `scen` from terrain node values at the corners of
  * the level-`dem_level` cells: dem_nodes[j * nx + i], nx = mi*m*2^dem_level+1,
  * ny = mj*m*2^dem_level+1.  Cell values integrate the bilinear interpolant of
- * the nodes (Section 5.3, integral-preserving topography): at levels >=
+ * the nodes (Section 6.2, integral-preserving topography): at levels >=
  * dem_level the interpolant's cell average, below it the mean of the four
  * children.  Errors: GF_E_INVALID on shape mismatch. */
 int gf_set_bathymetry(gf_ctx *ctx, int32_t scen, const double *dem_nodes, int64_t nx, int64_t ny,
@@ -145,7 +145,7 @@ int gf_step(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *
 
 /* Refinement flags of every leaf of every scenario, concatenated in scenario
  * then leaf order: +1 refine, -1 coarsen, 0 keep (the depth, free-surface
- * gradient and advancing-front criteria of Section 4, with halved thresholds
+ * gradient and advancing-front criteria of Section 4.1, with halved thresholds
  * for coarsening).  Decided in FP64 with + - and compares only.  `flags_out`
  * is nullable (the flags are kept for gf_regrid). */
 int gf_tag(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
@@ -165,6 +165,20 @@ int gf_mass(gf_ctx *ctx, int32_t scen, double *mass, double *clamp_volume, doubl
 /* Clock of a scenario. */
 int gf_time(gf_ctx *ctx, int32_t scen, double *t, double *dt_next, int64_t *steps, int64_t *rejected);
 int gf_set_time(gf_ctx *ctx, int32_t scen, double t, double dt_next);
+
+/* Workgroup size of the step kernel (one workgroup per patch).  Built
+ * sizes: m = 32: 256 or 512 threads; m = 16: 64 or 128.  The default is the
+ * smaller one; a tuner times the candidates and sets the faster.  Results do
+ * not depend on the choice (same arithmetic per cell).
+ * Errors: GF_E_UNSUPPORTED for a size that is not built. */
+int gf_set_step_threads(gf_ctx *ctx, int32_t nt);
+int gf_get_step_threads(gf_ctx *ctx, int32_t *nt);
+/* Schedule of the step kernel.  workgroups = -1 (default): as many
+ * persistent workgroups as the GPU holds at once, each taking patches of
+ * every level and scenario from a device queue until it is empty; k > 0: at
+ * most k persistent workgroups; 0: one workgroup per patch.  Results do not
+ * depend on the choice.  Errors: GF_E_INVALID for workgroups < -1. */
+int gf_set_schedule(gf_ctx *ctx, int32_t workgroups);
 
 /* Time the step kernel with HIP events on the context stream: when enabled,
  * every step-kernel launch is bracketed by events and gf_profile_read

@@ -19,9 +19,9 @@
  *   - quadtree of fixed-size patches, refinement ratio 2, no skipped
  *     levels, effective resolution: Section 4;
  *   - inflow ghost cells from eq. (riemann) / eq. (2-shock) by Newton:
- *     Section 4.1.1 (Test Case 1 set-up);
- *   - depth/gradient refinement criteria: Section 4 ("GeoFlood refinement
- *     criteria"); integral-preserving topography: Section 5.3.
+ *     Section 5.1.1 (Test Case 1 set-up);
+ *   - depth/gradient refinement criteria: Section 4.1 ("GeoFlood refinement
+ *     criteria"); integral-preserving topography: Section 6.2.
  * Where the paper is silent the numbered readings (R1..R40) of the design
  * notes are implemented; each function names the reading it takes.
  *
@@ -157,7 +157,7 @@ static int find_cover(const orc_sim *s, int l, long I, long J, int *rel)
 }
 
 /* ------------------------------------------------------------------------ */
-/* bathymetry (Section 5.3: integral of a unique interpolant; reading R12)   */
+/* bathymetry (Section 6.2: integral of a unique interpolant; reading R12)   */
 /* ------------------------------------------------------------------------ */
 
 static double dem_node(const orc_sim *s, long i, long j) { return s->dem[j * s->dem_nx + i]; }
@@ -488,7 +488,7 @@ double orc_cbrt(double x)
 }
 
 /* ------------------------------------------------------------------------ */
-/* inflow ghost state (Section 4.1.1, eq. riemann and eq. 2-shock)           */
+/* inflow ghost state (Section 5.1.1, eq. riemann and eq. 2-shock)           */
 /* ------------------------------------------------------------------------ */
 
 double orc_hydrograph(const orc_sim *s, double t)
@@ -1380,7 +1380,7 @@ void orc_mass(const orc_sim *s, double out[3])
 }
 
 /* ------------------------------------------------------------------------ */
-/* refinement criteria (Section 4 list; readings R20-R22)                    */
+/* refinement criteria (Section 4.1 list; readings R20-R22)                    */
 /* ------------------------------------------------------------------------ */
 
 static int cell_criterion(const orc_sim *s, const leaf_t *L, int i, int j, double Hr, double Er)

@@ -43,8 +43,8 @@ class gf_step_stats(C.Structure):
 
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step",
-           "gf_tag", "gf_regrid", "gf_mass", "gf_time", "gf_set_time", "gf_profile_enable", "gf_profile_read",
-           "gf_last_error", "gf_version"]
+           "gf_tag", "gf_regrid", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
+           "gf_get_step_threads", "gf_set_schedule", "gf_profile_enable", "gf_profile_read", "gf_last_error", "gf_version"]
 
 _lib = None
 
@@ -82,6 +82,9 @@ def load(path: str = LIB_PATH):
     L.gf_mass.argtypes = [vp, i32, dp, dp, dp]
     L.gf_time.argtypes = [vp, i32, dp, dp, C.POINTER(i64), C.POINTER(i64)]
     L.gf_set_time.argtypes = [vp, i32, C.c_double, C.c_double]
+    L.gf_set_step_threads.argtypes = [vp, i32]
+    L.gf_get_step_threads.argtypes = [vp, C.POINTER(i32)]
+    L.gf_set_schedule.argtypes = [vp, i32]
     L.gf_profile_enable.argtypes = [vp, i32]
     L.gf_profile_read.argtypes = [vp, C.POINTER(i64), dp]
     L.gf_last_error.argtypes = [vp]
@@ -255,6 +258,18 @@ class Context:
 
     def set_time(self, scen: int, t: float, dt_next: float = 0.0):
         self._chk(self.L.gf_set_time(self._p, scen, t, dt_next))
+
+    def set_step_threads(self, nt: int):
+        self._chk(self.L.gf_set_step_threads(self._p, nt))
+
+    def set_schedule(self, workgroups: int = -1):
+        """-1: resident persistent grid; k > 0: k persistent workgroups; 0: one per patch."""
+        self._chk(self.L.gf_set_schedule(self._p, int(workgroups)))
+
+    def step_threads(self) -> int:
+        n = C.c_int32()
+        self._chk(self.L.gf_get_step_threads(self._p, C.byref(n)))
+        return n.value
 
     def profile_enable(self, on: bool = True):
         self._chk(self.L.gf_profile_enable(self._p, 1 if on else 0))

@@ -23,6 +23,22 @@ UNITS = [
 ]
 
 
+def source_digest() -> str:
+    """SHA-256 over the kernel and host sources and the compile flags; names the
+    exact code a profile was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(" ".join(COMMON).encode())
+    for src, extra in UNITS:
+        h.update(" ".join(extra).encode())
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".inc", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
 def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l and l.strip())
@@ -47,4 +63,7 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--digest" in sys.argv:
+        print(source_digest())
+    else:
+        print(build(verbose="-v" in sys.argv))

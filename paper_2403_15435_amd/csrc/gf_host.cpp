@@ -55,6 +55,12 @@ struct gf_ctx {
     gf_config cfg{};
     int prec = GF_FP64;
     int m = 32;
+    int step_threads = 256;   // workgroup size of the step kernel
+    int sched_wg = -1;        // step workgroups: 0 one per patch, > 0 that many persistent, -1 the resident count
+    int resident[2] = {0, 0}; // resident workgroup count per step-thread choice (cached)
+    uint8_t *dry[2] = {nullptr, nullptr};   // per slot and buffer: all interior cells dry
+    unsigned *d_queue = nullptr;
+    bool flags_dirty = true;  // state changed from the host: recompute the dry flags
     size_t es = 8;
     hipStream_t stream = nullptr;
     std::vector<Scen> sc;
@@ -117,7 +123,7 @@ inline int ring_size(int m) { return (m + 4) * (m + 4) - m * m; }
 
 // ---------------------------------------------------------------- bathymetry
 // Cell bathymetry at level l, cell (I, J): integral of the bilinear terrain
-// interpolant over the cell (Section 5.3).  Four-point means pair diagonal
+// interpolant over the cell (Section 6.2).  Four-point means pair diagonal
 // corners so that the result is invariant under exchange of the axes.
 double bathy(const gf_ctx *c, const Scen &s, int l, int64_t I, int64_t J)
 {
@@ -384,10 +390,50 @@ int ensure_work(gf_ctx *c)
 // element access helpers for the state buffers
 inline size_t fstride(const gf_ctx *c) { return (size_t)c->cap * c->m * c->m; }
 
+float tau32(double tau)
+{
+    float tf = (float)tau;
+    if ((double)tf > tau) tf = std::nextafter(tf, 0.0f);
+    return tf;
+}
+
+int refresh_dry_flags(gf_ctx *c)
+{
+    if (!c->flags_dirty) return GF_OK;
+    const int n = (int)c->desc.size();
+    hipError_t e;
+    if (c->prec == GF_FP32)
+        e = gf_launch_dryflag_f32(c->d_desc, n, c->d_scen, (const float *)c->q[0], (const float *)c->q[1], c->dry[0],
+                                  c->dry[1], c->cap, tau32(c->cfg.dry_tol), c->m, c->stream);
+    else
+        e = gf_launch_dryflag_f64(c->d_desc, n, c->d_scen, (const double *)c->q[0], (const double *)c->q[1], c->dry[0],
+                                  c->dry[1], c->cap, c->cfg.dry_tol, c->m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "dry-flag launch: %s", hipGetErrorString(e));
+    c->flags_dirty = false;
+    return GF_OK;
+}
+
 int launch_step(gf_ctx *c, double dt_fixed, int mode)
 {
     const int n = (int)c->desc.size();
     hipError_t e;
+    if (mode != 2) {
+        int rc = refresh_dry_flags(c);
+        if (rc) return rc;
+    }
+    // workgroups: one per patch, or the resident count taking patches from the queue
+    int grid = n;
+    if (c->sched_wg != 0 && mode != 2) {
+        int want = c->sched_wg;
+        if (want < 0) {
+            const int ki = c->step_threads == (c->m == 16 ? 64 : 256) ? 0 : 1;
+            if (c->resident[ki] <= 0)
+                c->resident[ki] = c->prec == GF_FP32 ? gf_step_resident_f32(c->m, c->step_threads)
+                                                     : gf_step_resident_f64(c->m, c->step_threads);
+            want = c->resident[ki];
+        }
+        if (want > 0 && want < n) grid = want;
+    }
     const bool timed = c->prof && mode == 0;
     size_t evk = 0;
     if (timed) {
@@ -406,10 +452,9 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
         a.reg = (float *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
         a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
-        float tf = (float)c->cfg.dry_tol;
-        if ((double)tf > c->cfg.dry_tol) tf = std::nextafter(tf, 0.0f);
-        a.tau = tf; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = (float *)c->ghost;
-        e = gf_launch_step_f32(a, c->m, c->stream);
+        a.tau = tau32(c->cfg.dry_tol); a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = (float *)c->ghost;
+        a.queue = c->d_queue; a.persistent = grid < n ? 1 : 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
+        e = gf_launch_step_f32(a, c->m, c->step_threads, grid, c->stream);
     } else {
         StepArgs<double> a{};
         a.desc = c->d_desc; a.n_work = n; a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
@@ -418,7 +463,8 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         a.reg = (double *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
         a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
         a.tau = c->cfg.dry_tol; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = (double *)c->ghost;
-        e = gf_launch_step_f64(a, c->m, c->stream);
+        a.queue = c->d_queue; a.persistent = grid < n ? 1 : 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
+        e = gf_launch_step_f64(a, c->m, c->step_threads, grid, c->stream);
     }
     if (e != hipSuccess) return fail(c, GF_E_HIP, "step launch: %s", hipGetErrorString(e));
     if (timed) {
@@ -429,9 +475,9 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         RefluxArgsBase r{};
         r.tasks = c->d_reflux; r.n_tasks = (int)c->reflux.size(); r.scen = c->d_scen; r.cap = c->cap; r.tau64 = c->cfg.dry_tol;
         if (c->prec == GF_FP32)
-            e = gf_launch_reflux_f32(r, (float *)c->q[0], (float *)c->q[1], (const float *)c->reg, c->cacc[0], c->cacc[1], c->m, c->stream);
+            e = gf_launch_reflux_f32(r, (float *)c->q[0], (float *)c->q[1], (const float *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
         else
-            e = gf_launch_reflux_f64(r, (double *)c->q[0], (double *)c->q[1], (const double *)c->reg, c->cacc[0], c->cacc[1], c->m, c->stream);
+            e = gf_launch_reflux_f64(r, (double *)c->q[0], (double *)c->q[1], (const double *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "reflux launch: %s", hipGetErrorString(e));
     }
     return GF_OK;
@@ -504,6 +550,7 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     c->cfg.scen = nullptr;
     c->prec = cfg->precision;
     c->m = cfg->m;
+    c->step_threads = cfg->m == 16 ? 64 : 256;
     c->es = c->prec == GF_FP32 ? 4 : 8;
     c->stream = (hipStream_t)cfg->hip_stream;
     c->cap = cfg->max_patches;
@@ -544,7 +591,9 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     ok = ok && alloc(&c->reg, (size_t)4 * c->cap * c->m * 3 * c->es);
     ok = ok && alloc((void **)&c->cacc[0], sizeof(double) * c->cap) && alloc((void **)&c->cacc[1], sizeof(double) * c->cap);
     ok = ok && alloc((void **)&c->bacc[0], sizeof(double) * c->cap) && alloc((void **)&c->bacc[1], sizeof(double) * c->cap);
-    ok = ok && alloc((void **)&c->d_scen, sizeof(ScenDev) * c->sc.size()) && alloc((void **)&c->d_counter, 64);
+    ok = ok && alloc((void **)&c->d_scen, sizeof(ScenDev) * c->sc.size()) && alloc((void **)&c->d_counter, 64 * ((size_t)c->cap / 64 + 2));
+    ok = ok && alloc((void **)&c->d_queue, 64) && alloc((void **)&c->dry[0], (size_t)c->cap) &&
+         alloc((void **)&c->dry[1], (size_t)c->cap);
     ok = ok && alloc((void **)&c->d_thr, sizeof(double) * 2 * c->sc.size()) && alloc((void **)&c->d_lev, sizeof(int32_t) * 2 * c->sc.size());
     if (!ok) {
         gf_destroy(c);
@@ -572,7 +621,8 @@ void gf_destroy(gf_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
-                  c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer};
+                  c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
+                  c->d_queue, c->dry[0], c->dry[1]};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -646,6 +696,7 @@ int gf_set_leaves(gf_ctx *c, int32_t scen, const int32_t *tlxy, int64_t n)
     rc = upload_bathy(c, s, all);
     if (rc) return rc;
     c->topo_dirty = true;
+    c->flags_dirty = true;
     rc = ensure_work(c);
     if (rc) { c->topo_dirty = true; return rc; }
     s.clamp_base = 0.0;
@@ -691,6 +742,7 @@ static int patch_io(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, double
         else to_real<double>(buf, (double *)tmp.data(), MM);
         HIPCHK(c, hipMemcpyAsync(dev, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (field == 0) c->flags_dirty = true;
     } else {
         HIPCHK(c, hipMemcpyAsync(tmp.data(), dev, tmp.size(), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -718,16 +770,19 @@ int gf_set_state(gf_ctx *c, int32_t scen, const double *in)
     const Scen &s = c->sc[(size_t)scen];
     const size_t MM = (size_t)c->m * c->m;
     const int cur = c->hs[(size_t)scen].cur;
-    std::vector<char> tmp(MM * c->es);
+    // stage everything, queue the copies, wait once
+    std::vector<char> tmp(s.leaves.size() * 3 * MM * c->es);
     for (size_t k = 0; k < s.leaves.size(); ++k)
         for (int f = 0; f < 3; ++f) {
             const double *src = in + (k * 3 + (size_t)f) * MM;
-            if (c->prec == GF_FP32) to_real<float>(src, (float *)tmp.data(), MM);
-            else to_real<double>(src, (double *)tmp.data(), MM);
+            char *stage = tmp.data() + (k * 3 + (size_t)f) * MM * c->es;
+            if (c->prec == GF_FP32) to_real<float>(src, (float *)stage, MM);
+            else to_real<double>(src, (double *)stage, MM);
             char *dev = (char *)c->q[cur] + ((size_t)f * fstride(c) + (size_t)s.leaves[k].slot * MM) * c->es;
-            HIPCHK(c, hipMemcpyAsync(dev, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
+            HIPCHK(c, hipMemcpyAsync(dev, stage, MM * c->es, hipMemcpyHostToDevice, c->stream));
         }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->flags_dirty = true;
     return GF_OK;
 }
 
@@ -1050,6 +1105,7 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
     }
     for (int32_t sl : freed) give_slot(c, sl);
     c->topo_dirty = true;
+    c->flags_dirty = true;
     rc = ensure_work(c);
     if (rc) return rc;
     if (n_leaves) *n_leaves = total;
@@ -1109,6 +1165,29 @@ int gf_set_time(gf_ctx *c, int32_t scen, double t, double dt_next)
     c->hs[(size_t)scen].t = t;
     c->hs[(size_t)scen].dt = dt_next;
     return push_scen(c);
+}
+
+int gf_set_step_threads(gf_ctx *c, int32_t nt)
+{
+    if (!c) return GF_E_INVALID;
+    const int ok = c->prec == GF_FP32 ? gf_step_threads_ok_f32(c->m, nt) : gf_step_threads_ok_f64(c->m, nt);
+    if (!ok) return fail(c, GF_E_UNSUPPORTED, "no step kernel built for m = %d with %d threads", c->m, nt);
+    c->step_threads = nt;
+    return GF_OK;
+}
+
+int gf_set_schedule(gf_ctx *c, int32_t workgroups)
+{
+    if (!c || workgroups < -1) return GF_E_INVALID;
+    c->sched_wg = workgroups;
+    return GF_OK;
+}
+
+int gf_get_step_threads(gf_ctx *c, int32_t *nt)
+{
+    if (!c || !nt) return GF_E_INVALID;
+    *nt = c->step_threads;
+    return GF_OK;
 }
 
 int gf_profile_enable(gf_ctx *c, int32_t on)

@@ -79,7 +79,10 @@ struct StepArgs {
     double g, cfl_desired, cfl_max;
     R tau;                   // dry iff h <= tau (tau rounded down to R)
     double tau64;
-    unsigned int *done_counter;
+    unsigned int *done_counter;  // [0] groups done; [16 (1 + g)] workgroups done in group g (64 per group)
+    unsigned int *queue;         // next work item (persistent form); reset to 0 by the last workgroup
+    int32_t persistent;          // 1: resident workgroups take items from the queue
+    uint8_t *dry0, *dry1;        // per slot and buffer: 1 iff every interior cell has h <= tau
     R *ghost_out;            // gf_fill_ghosts: [cap][4][(m+4)^2], else null
 };
 
@@ -95,9 +98,15 @@ struct RefluxArgsBase {
 
 // Launchers, one set per precision (defined in gf_kernels_f32.hip / _f64.hip).
 #define GF_DECL_LAUNCHERS(SFX, R)                                                                  \
-    hipError_t gf_launch_step_##SFX(const gf::StepArgs<R> &a, int m, hipStream_t s);               \
+    hipError_t gf_launch_step_##SFX(const gf::StepArgs<R> &a, int m, int nt, int grid, hipStream_t s); \
+    int gf_step_threads_ok_##SFX(int m, int nt);                                                   \
+    int gf_step_resident_##SFX(int m, int nt);                                                     \
+    hipError_t gf_launch_dryflag_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,     \
+                                       const R *q0, const R *q1, uint8_t *f0, uint8_t *f1,         \
+                                       int64_t cap, R tau, int m, hipStream_t s);                  \
     hipError_t gf_launch_reflux_##SFX(const gf::RefluxArgsBase &a, R *q0, R *q1, const R *reg,     \
-                                      double *ca0, double *ca1, int m, hipStream_t s);             \
+                                      double *ca0, double *ca1, uint8_t *f0, uint8_t *f1, int m,   \
+                                      hipStream_t s);                                               \
     hipError_t gf_launch_tag_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,         \
                                    const R *q0, const R *q1, const R *b, int64_t cap,              \
                                    const double *thr, const int32_t *lev_limits, double tau64,     \

@@ -8,8 +8,8 @@ implemented separately by the library and by the CPU oracle.
 Terrain: value noise with quintic smoothstep interpolation of lattice values,
 lattice values drawn from SplitMix64(seed, octave, ix, iy) mapped to [-1, 1],
 5 octaves, lacunarity 2, persistence 0.5, base wavelength L/4.  The paper
-measures on real DEMs (the Malpasset CADAM terrain, Section 5) and on the
-UK Environment Agency benchmark geometries (Section 4); seeded fractal
+measures on real DEMs (the Malpasset CADAM terrain, Section 6) and on the
+UK Environment Agency benchmark geometries (Section 5); seeded fractal
 terrain of the same scale stands in for them here.
 """
 from __future__ import annotations
@@ -237,6 +237,26 @@ def reservoir_fractal(level: int = 6, m: int = 32, seed: int = 2, radius: float 
     def eta(X, Y, b):
         r = np.hypot(X - cx, Y - cy)
         return np.where(r <= radius, b + h_res, -1e9)
+    sc.eta_fn = eta
+    return sc
+
+
+def wet_dambreak(level: int = 6, m: int = 32, seed: int = 2, radius: float = 400.0,
+                 eta0: float = 155.0, eta1: float = 165.0, L: float = 10000.0,
+                 manning_n: float = 0.033) -> Scenario:
+    """The reservoir terrain (100 +/- 50 m) under a lake at eta0 = 155 m, so
+    every cell is wet, with a column raised to eta1 within `radius` of the
+    centre: a dam break on fully wet terrain."""
+    sc = Scenario(name=f"wet_dambreak_l{level}_m{m}", x0=0.0, y0=0.0, x1=L, y1=L, mi=1, mj=1, m=m,
+                  min_level=level, max_level=level, manning_n=manning_n, init_level=level)
+    nn = m * (1 << level) + 1
+    sc.dem = fractal_dem_nodes(nn, nn, L, L, seed, base=100.0, amp=50.0, norm="max")
+    sc.dem_level = level
+    cx = cy = 0.5 * L
+
+    def eta(X, Y, b):
+        r = np.hypot(X - cx, Y - cy)
+        return np.where(r <= radius, eta1, eta0) + 0.0 * b
     sc.eta_fn = eta
     return sc
 
