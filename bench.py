@@ -4,9 +4,11 @@ Workload (one step = one full pass of ghost fill + wave-propagation update +
 friction + positivity + step control over every patch): uniform 2048 x 2048
 cells as 64 x 64 patches of 32 x 32 on a 10 km square of seeded fractal
 terrain (100 +/- 50 m), circular reservoir of depth 20 m and radius 400 m,
-Manning n = 0.033, walls.  Reported beside it: the same run on the FP64
-path, the step kernel's HBM roofline fraction (algorithmic 28 B per FP32 cell
-update), and the CPU oracle timed on a bounded sample of the same workload.
+Manning n = 0.033, walls.  A step is two kernels: the classification and
+update of dry patches, then the full update of the others.  Reported beside
+it: the same run on the FP64 path, the step's HBM roofline fraction
+(algorithmic 28 B per FP32 cell update), the same grid fully wet, and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -40,10 +42,14 @@ def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False)
     import torch
     import paper_2403_15435_amd as gf
     ctx = gf.Context([sc], precision=precision, max_patches=4096)
-    if step_threads:
-        ctx.set_step_threads(step_threads)
     ctx.set_initial(0)
     ctx.step(warmup)
+    tuned = None
+    if step_threads:
+        ctx.set_step_threads(step_threads)
+    else:
+        # launch shape from the tuner (state restored after its trials)
+        tuned = ctx.autotune(steps=5)
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     t0 = time.perf_counter()
@@ -51,11 +57,13 @@ def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launches, ms = ctx.profile_read()
+    ms_dry, ms_step = ctx.profile_split()
     ctx.profile_enable(False)
     cells = int(st.cell_updates)
     mass = ctx.mass(0)
     out = {"wall": wall, "cell_updates": cells, "steps": int(st.steps), "launches": launches,
-           "kernel_ms": ms, "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads()}
+           "kernel_ms": ms, "dry_kernel_ms": ms_dry, "step_kernel_ms": ms_step,
+           "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads(), "tuned": tuned}
     if wet_fraction:
         h = ctx.state(0)[:, 0]
         out["wet_cell_fraction"] = float(np.count_nonzero(h > 1e-4)) / h.size
@@ -83,7 +91,7 @@ def cpu_baseline(sc, steps=48):
 
 
 def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed FETCH_SIZE /
+    """HBM bytes per step (both kernels) from the committed FETCH_SIZE /
     WRITE_SIZE counter summary, scaled by the copy-kernel calibration; None
     when the summary was taken on different kernel sources."""
     from paper_2403_15435_amd.build import source_digest
@@ -97,8 +105,8 @@ def measured_traffic():
     if kv.get("source_digest") != source_digest():
         return None
     try:
-        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
-        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+        fetch = float(kv["fetch_kib_per_step"]) * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_step"]) * float(kv["write_scale"])
     except (KeyError, ValueError):
         return None
     return (fetch + write) * 1024.0
@@ -123,7 +131,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--fp64-steps", type=int, default=500)
+    ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 run (0: the same as --steps)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--step-threads", type=int, default=0, help="step-kernel workgroup size (0: library default)")
     ap.add_argument("--wet-steps", type=int, default=200, help="steps of the all-wet comparison run (0: skip)")
@@ -142,6 +150,8 @@ def main():
     sc = workload()
     print(f"[bench] workload ready: {sc.name}, {4096} patches", file=sys.stderr, flush=True)
     nt = args.step_threads or None
+    if args.fp64_steps <= 0:
+        args.fp64_steps = args.steps
     if args.precision == "f64":
         r64 = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.fp64_steps, nt)
         print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
@@ -150,7 +160,7 @@ def main():
     print(f"[bench] fp32 done: {r32}", file=sys.stderr, flush=True)
     if args.precision == "f32":
         return
-    r64 = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.fp64_steps, nt)
+    r64 = run_gpu(sc, gf.GF_FP64, args.warmup, args.fp64_steps, nt)
     print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
     wet = None
     if args.wet_steps > 0:
@@ -162,8 +172,10 @@ def main():
         wet = {"workload": "same grid and terrain under a lake at 155 m (every cell wet), column at 165 m r=400 m",
                "fp32_cell_updates_per_s": w32["cell_updates"] / w32["wall"],
                "fp64_cell_updates_per_s": w64["cell_updates"] / w64["wall"],
-               "fp32_avg_launch_us": wl * 1e6,
-               "fp32_hbm_frac": BYTES_PER_UPDATE["f32"] * 4096 * 1024 / wl / 1e9 / HBM_PEAK_GBS}
+               "fp32_step_us": wl * 1e6,
+               "fp32_step_kernel_us": 1e3 * w32["step_kernel_ms"] / max(w32["launches"], 1),
+               "fp32_hbm_frac": BYTES_PER_UPDATE["f32"] * 4096 * 1024 / wl / 1e9 / HBM_PEAK_GBS,
+               "step_threads": w32["step_threads"]}
     cups32 = r32["cell_updates"] / r32["wall"]
     cups64 = r64["cell_updates"] / r64["wall"]
     cells_per_launch = 4096 * 32 * 32
@@ -184,7 +196,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (counters x copy calibration)",
                      "algorithmic_bytes_per_launch": BYTES_PER_UPDATE["f32"] * cells_per_launch,
-                     "kernel": "step_kernel<32,256> (fp32)", "avg_launch_us": avg_launch_s * 1e6},
+                     "kernel": f"one step = dry_kernel<32> + step_kernel<32,{r32['step_threads']}> (fp32)",
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "dry_kernel_us": 1e3 * r32["dry_kernel_ms"] / max(r32["launches"], 1),
+                     "step_kernel_us": 1e3 * r32["step_kernel_ms"] / max(r32["launches"], 1)},
         "fp64_plain": {"value": cups64, "unit": "cell-updates/s", "steps": r64["steps"],
                        "speedup_fp32_over_fp64": cups32 / cups64},
         "cpu_baseline": cpu,

@@ -167,12 +167,23 @@ int gf_time(gf_ctx *ctx, int32_t scen, double *t, double *dt_next, int64_t *step
 int gf_set_time(gf_ctx *ctx, int32_t scen, double t, double dt_next);
 
 /* Workgroup size of the step kernel (one workgroup per patch).  Built
- * sizes: m = 32: 256 or 512 threads; m = 16: 64 or 128.  The default is the
+ * sizes: m = 32: 256, 512 or 1024 threads; m = 16: 64, 128 or 256.  The default is the
  * smaller one; a tuner times the candidates and sets the faster.  Results do
  * not depend on the choice (same arithmetic per cell).
  * Errors: GF_E_UNSUPPORTED for a size that is not built. */
 int gf_set_step_threads(gf_ctx *ctx, int32_t nt);
 int gf_get_step_threads(gf_ctx *ctx, int32_t *nt);
+/* Autotuner: time every built step-kernel shape (workgroup size x schedule)
+ * for `steps` steps on the context's current state, keep the fastest, and
+ * restore the state, clocks and budgets after each trial, so the simulation
+ * is unchanged.  cache_path (nullable): a text file of earlier choices keyed
+ * by GPU architecture, precision, patch size and patch count (rounded up to a
+ * power of two); a hit skips the timing (us_per_step is then -1), a miss
+ * appends the new choice.  Outputs are nullable.
+ * Errors: GF_E_INVALID, GF_E_STATE (no bathymetry or leaves), GF_E_HIP. */
+int gf_autotune(gf_ctx *ctx, int32_t steps, const char *cache_path, int32_t *threads, int32_t *schedule,
+                double *us_per_step);
+
 /* Schedule of the step kernel.  workgroups = -1 (default): as many
  * persistent workgroups as the GPU holds at once, each taking patches of
  * every level and scenario from a device queue until it is empty; k > 0: at
@@ -180,11 +191,14 @@ int gf_get_step_threads(gf_ctx *ctx, int32_t *nt);
  * depend on the choice.  Errors: GF_E_INVALID for workgroups < -1. */
 int gf_set_schedule(gf_ctx *ctx, int32_t workgroups);
 
-/* Time the step kernel with HIP events on the context stream: when enabled,
- * every step-kernel launch is bracketed by events and gf_profile_read
- * returns the number of launches and their summed duration (ms). */
+/* Time the step with HIP events on the context stream.  A step is two
+ * kernels: the classification and update of dry patches, then the full
+ * update of the others.  When enabled, events bracket both; gf_profile_read
+ * returns the number of steps and their summed duration (ms), and
+ * gf_profile_split the two kernels' shares of the last read. */
 int gf_profile_enable(gf_ctx *ctx, int32_t on);
 int gf_profile_read(gf_ctx *ctx, int64_t *launches, double *ms_total);
+int gf_profile_split(gf_ctx *ctx, double *ms_dry, double *ms_step);
 
 /* Description of the last failure on this context (static storage, valid
  * until the next call on it). */

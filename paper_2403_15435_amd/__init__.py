@@ -44,7 +44,7 @@ class gf_step_stats(C.Structure):
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step",
            "gf_tag", "gf_regrid", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
-           "gf_get_step_threads", "gf_set_schedule", "gf_profile_enable", "gf_profile_read", "gf_last_error", "gf_version"]
+           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_split", "gf_last_error", "gf_version"]
 
 _lib = None
 
@@ -85,8 +85,10 @@ def load(path: str = LIB_PATH):
     L.gf_set_step_threads.argtypes = [vp, i32]
     L.gf_get_step_threads.argtypes = [vp, C.POINTER(i32)]
     L.gf_set_schedule.argtypes = [vp, i32]
+    L.gf_autotune.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(i32), dp]
     L.gf_profile_enable.argtypes = [vp, i32]
     L.gf_profile_read.argtypes = [vp, C.POINTER(i64), dp]
+    L.gf_profile_split.argtypes = [vp, dp, dp]
     L.gf_last_error.argtypes = [vp]
     L.gf_last_error.restype = C.c_char_p
     L.gf_version.restype = C.c_char_p
@@ -266,6 +268,14 @@ class Context:
         """-1: resident persistent grid; k > 0: k persistent workgroups; 0: one per patch."""
         self._chk(self.L.gf_set_schedule(self._p, int(workgroups)))
 
+    def autotune(self, steps: int = 5, cache: Optional[str] = None):
+        """Time the step kernel's launch shapes on the current state and keep
+        the fastest (state unchanged).  Returns (threads, schedule, us_per_step)."""
+        nt, sc, us = C.c_int32(), C.c_int32(), C.c_double()
+        self._chk(self.L.gf_autotune(self._p, steps, cache.encode() if cache else None,
+                                     C.byref(nt), C.byref(sc), C.byref(us)))
+        return nt.value, sc.value, us.value
+
     def step_threads(self) -> int:
         n = C.c_int32()
         self._chk(self.L.gf_get_step_threads(self._p, C.byref(n)))
@@ -278,6 +288,12 @@ class Context:
         n, ms = C.c_int64(), C.c_double()
         self._chk(self.L.gf_profile_read(self._p, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+    def profile_split(self):
+        """(ms in the dry-patch kernel, ms in the full step kernel) of the last profile_read."""
+        d, w = C.c_double(), C.c_double()
+        self._chk(self.L.gf_profile_split(self._p, C.byref(d), C.byref(w)))
+        return d.value, w.value
 
     # ------------------------------------------------------------ helpers
     def set_initial(self, scen: int = 0, precision: Optional[str] = None):

@@ -57,8 +57,11 @@ struct gf_ctx {
     int m = 32;
     int step_threads = 256;   // workgroup size of the step kernel
     int sched_wg = -1;        // step workgroups: 0 one per patch, > 0 that many persistent, -1 the resident count
-    int resident[2] = {0, 0}; // resident workgroup count per step-thread choice (cached)
+    int resident[3] = {0, 0, 0}; // resident workgroup count per step-thread choice (cached)
     uint8_t *dry[2] = {nullptr, nullptr};   // per slot and buffer: all interior cells dry
+    int32_t *d_wet = nullptr;                // wet work items of the current step
+    unsigned *d_wet_count = nullptr;
+    double prof_ms_dry = 0.0, prof_ms_step = 0.0;
     unsigned *d_queue = nullptr;
     bool flags_dirty = true;  // state changed from the host: recompute the dry flags
     size_t es = 8;
@@ -426,7 +429,8 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
     if (c->sched_wg != 0 && mode != 2) {
         int want = c->sched_wg;
         if (want < 0) {
-            const int ki = c->step_threads == (c->m == 16 ? 64 : 256) ? 0 : 1;
+            const int base = c->m == 16 ? 64 : 256;
+            const int ki = c->step_threads == base ? 0 : (c->step_threads == 2 * base ? 1 : 2);
             if (c->resident[ki] <= 0)
                 c->resident[ki] = c->prec == GF_FP32 ? gf_step_resident_f32(c->m, c->step_threads)
                                                      : gf_step_resident_f64(c->m, c->step_threads);
@@ -437,38 +441,46 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
     const bool timed = c->prof && mode == 0;
     size_t evk = 0;
     if (timed) {
-        evk = (size_t)c->prof_launches * 2;
-        while (c->ev.size() < evk + 2) {
+        evk = (size_t)c->prof_launches * 3;
+        while (c->ev.size() < evk + 3) {
             hipEvent_t x;
             HIPCHK(c, hipEventCreate(&x));
             c->ev.push_back(x);
         }
         HIPCHK(c, hipEventRecord(c->ev[evk], c->stream));
     }
+    // dry_kernel (classification and the dry update) then step_kernel on the
+    // wet list; a ghost fill (mode 2) runs step_kernel on every patch
+    auto fill = [&](auto &a, auto *q0, auto *q1, auto *b, auto *bg, auto *reg, auto *ghost, auto tau) {
+        a.desc = c->d_desc; a.n_work = n; a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
+        a.q0 = q0; a.q1 = q1; a.b = b; a.bg = bg;
+        a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
+        a.reg = reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
+        a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
+        a.tau = tau; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = ghost;
+        a.queue = c->d_queue; a.persistent = grid < n ? 1 : 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
+        a.wet_list = c->d_wet; a.wet_count = c->d_wet_count; a.all_items = mode == 2 ? 1 : 0;
+    };
     if (c->prec == GF_FP32) {
         StepArgs<float> a{};
-        a.desc = c->d_desc; a.n_work = n; a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
-        a.q0 = (float *)c->q[0]; a.q1 = (float *)c->q[1]; a.b = (const float *)c->b; a.bg = (const float *)c->bg;
-        a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
-        a.reg = (float *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
-        a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
-        a.tau = tau32(c->cfg.dry_tol); a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = (float *)c->ghost;
-        a.queue = c->d_queue; a.persistent = grid < n ? 1 : 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
+        fill(a, (float *)c->q[0], (float *)c->q[1], (const float *)c->b, (const float *)c->bg, (float *)c->reg,
+             (float *)c->ghost, tau32(c->cfg.dry_tol));
+        e = mode == 2 ? hipSuccess : gf_launch_dry_f32(a, c->m, c->stream);
+        if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
+        if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f32(a, c->m, c->step_threads, grid, c->stream);
     } else {
         StepArgs<double> a{};
-        a.desc = c->d_desc; a.n_work = n; a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
-        a.q0 = (double *)c->q[0]; a.q1 = (double *)c->q[1]; a.b = (const double *)c->b; a.bg = (const double *)c->bg;
-        a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
-        a.reg = (double *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
-        a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
-        a.tau = c->cfg.dry_tol; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = (double *)c->ghost;
-        a.queue = c->d_queue; a.persistent = grid < n ? 1 : 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
+        fill(a, (double *)c->q[0], (double *)c->q[1], (const double *)c->b, (const double *)c->bg, (double *)c->reg,
+             (double *)c->ghost, c->cfg.dry_tol);
+        e = mode == 2 ? hipSuccess : gf_launch_dry_f64(a, c->m, c->stream);
+        if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
+        if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f64(a, c->m, c->step_threads, grid, c->stream);
     }
     if (e != hipSuccess) return fail(c, GF_E_HIP, "step launch: %s", hipGetErrorString(e));
     if (timed) {
-        HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[evk + 2], c->stream));
         c->prof_launches++;
     }
     if (mode == 0 && !c->reflux.empty()) {
@@ -594,6 +606,7 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     ok = ok && alloc((void **)&c->d_scen, sizeof(ScenDev) * c->sc.size()) && alloc((void **)&c->d_counter, 64 * ((size_t)c->cap / 64 + 2));
     ok = ok && alloc((void **)&c->d_queue, 64) && alloc((void **)&c->dry[0], (size_t)c->cap) &&
          alloc((void **)&c->dry[1], (size_t)c->cap);
+    ok = ok && alloc((void **)&c->d_wet, sizeof(int32_t) * (size_t)c->cap) && alloc((void **)&c->d_wet_count, 64);
     ok = ok && alloc((void **)&c->d_thr, sizeof(double) * 2 * c->sc.size()) && alloc((void **)&c->d_lev, sizeof(int32_t) * 2 * c->sc.size());
     if (!ok) {
         gf_destroy(c);
@@ -622,7 +635,7 @@ void gf_destroy(gf_ctx *c)
     else (void)hipDeviceSynchronize();
     void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
-                  c->d_queue, c->dry[0], c->dry[1]};
+                  c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1190,6 +1203,163 @@ int gf_get_step_threads(gf_ctx *c, int32_t *nt)
     return GF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: time the step kernel's launch shapes on the context's own state
+// and keep the fastest.  The state, clocks and accumulators are restored after
+// every trial, so tuning does not change the simulation.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TuneKey {
+    std::string text;
+};
+
+TuneKey tune_key(const gf_ctx *c)
+{
+    int64_t n = (int64_t)c->desc.size();
+    int64_t bucket = 1;
+    while (bucket < n) bucket <<= 1;   // patch count rounded up to a power of two
+    char buf[160];
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    snprintf(buf, sizeof buf, "%s/%s/m%d/n%lld", arch.c_str(), c->prec == GF_FP32 ? "fp32" : "fp64", c->m,
+             (long long)bucket);
+    return TuneKey{buf};
+}
+
+// cache file: one line per key, "key threads sched us_per_step"
+bool cache_lookup(const char *path, const std::string &key, int *nt, int *sched)
+{
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char k[200];
+    int a = 0, b = 0;
+    double us = 0.0;
+    bool found = false;
+    while (fscanf(f, "%199s %d %d %lf", k, &a, &b, &us) == 4)
+        if (key == k) { *nt = a; *sched = b; found = true; }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int nt, int sched, double us)
+{
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %.3f\n", key.c_str(), nt, sched, us);
+    fclose(f);
+}
+
+}  // namespace
+
+int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threads_out, int32_t *sched_out,
+                double *us_per_step_out)
+{
+    if (!c || steps <= 0) return GF_E_INVALID;
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    const TuneKey key = tune_key(c);
+    int best_nt = c->step_threads, best_sched = c->sched_wg;
+    double best_us = -1.0;
+    if (cache_lookup(cache_path, key.text, &best_nt, &best_sched)) {
+        rc = gf_set_step_threads(c, best_nt);
+        if (rc) return rc;
+        c->sched_wg = best_sched;
+        if (threads_out) *threads_out = best_nt;
+        if (sched_out) *sched_out = best_sched;
+        if (us_per_step_out) *us_per_step_out = -1.0;
+        return GF_OK;
+    }
+    // snapshot everything a step changes
+    rc = pull_scen(c);
+    if (rc) return rc;
+    const std::vector<ScenDev> hs0 = c->hs;
+    const size_t qbytes = 3 * (size_t)c->m * c->m * (size_t)c->cap * c->es;
+    const size_t abytes = sizeof(double) * (size_t)c->cap;
+    std::vector<std::pair<void *, size_t>> parts = {{c->q[0], qbytes}, {c->q[1], qbytes},
+                                                    {c->cacc[0], abytes}, {c->cacc[1], abytes},
+                                                    {c->bacc[0], abytes}, {c->bacc[1], abytes},
+                                                    {c->dry[0], (size_t)c->cap}, {c->dry[1], (size_t)c->cap}};
+    size_t total = 0;
+    for (auto &p : parts) total += (p.second + 255) & ~(size_t)255;
+    char *snap = nullptr;
+    HIPCHK(c, hipMalloc((void **)&snap, total));
+    auto copy_all = [&](bool save) -> hipError_t {
+        size_t off = 0;
+        for (auto &p : parts) {
+            hipError_t e = save ? hipMemcpyAsync(snap + off, p.first, p.second, hipMemcpyDeviceToDevice, c->stream)
+                                : hipMemcpyAsync(p.first, snap + off, p.second, hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return e;
+            off += (p.second + 255) & ~(size_t)255;
+        }
+        return hipSuccess;
+    };
+    const bool flags_dirty0 = c->flags_dirty;
+    const int nt0 = c->step_threads, sched0 = c->sched_wg;
+    const bool prof0 = c->prof;
+    hipError_t e = copy_all(true);
+    static const int cand32[] = {256, 512, 1024}, cand16[] = {64, 128, 256};
+    const int *cand = c->m == 16 ? cand16 : cand32;
+    const int scheds[] = {-1, 0};
+    for (int ci = 0; ci < 3 && e == hipSuccess && rc == GF_OK; ++ci)
+        for (int si = 0; si < 2 && rc == GF_OK; ++si) {
+            c->step_threads = cand[ci];
+            c->sched_wg = scheds[si];
+            // one untimed step (first use of the shape), then the timed ones
+            c->prof = false;
+            rc = gf_step(c, 1, nullptr, nullptr);
+            if (rc == GF_OK) {
+                c->prof = true;
+                c->prof_launches = 0;
+                rc = gf_step(c, steps, nullptr, nullptr);
+            }
+            int64_t n = 0;
+            double ms = 0.0;
+            if (rc == GF_OK) rc = gf_profile_read(c, &n, &ms);
+            if (rc == GF_OK && n > 0) {
+                const double us = 1e3 * ms / (double)n;
+                if (best_us < 0.0 || us < best_us) { best_us = us; best_nt = cand[ci]; best_sched = scheds[si]; }
+            }
+            // restore
+            c->hs = hs0;
+            if ((e = copy_all(false)) != hipSuccess) break;
+            int r2 = push_scen(c);
+            if (rc == GF_OK) rc = r2;
+            c->flags_dirty = flags_dirty0;
+        }
+    c->prof = prof0;
+    c->prof_launches = 0;
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(snap);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "autotune snapshot: %s", hipGetErrorString(e));
+    if (rc != GF_OK) { c->step_threads = nt0; c->sched_wg = sched0; return rc; }
+    c->step_threads = best_nt;
+    c->sched_wg = best_sched;
+    cache_store(cache_path, key.text, best_nt, best_sched, best_us);
+    if (threads_out) *threads_out = best_nt;
+    if (sched_out) *sched_out = best_sched;
+    if (us_per_step_out) *us_per_step_out = best_us;
+    return GF_OK;
+}
+
+int gf_profile_split(gf_ctx *c, double *ms_dry, double *ms_step)
+{
+    if (!c) return GF_E_INVALID;
+    if (ms_dry) *ms_dry = c->prof_ms_dry;
+    if (ms_step) *ms_step = c->prof_ms_step;
+    return GF_OK;
+}
+
 int gf_profile_enable(gf_ctx *c, int32_t on)
 {
     if (!c) return GF_E_INVALID;
@@ -1202,14 +1372,17 @@ int gf_profile_read(gf_ctx *c, int64_t *launches, double *ms_total)
 {
     if (!c) return GF_E_INVALID;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double ms = 0.0;
+    double ms = 0.0, md = 0.0, mw = 0.0;
     for (int64_t k = 0; k < c->prof_launches; ++k) {
-        float x = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&x, c->ev[(size_t)(2 * k)], c->ev[(size_t)(2 * k + 1)]));
-        ms += x;
+        float x = 0.f, y = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&x, c->ev[(size_t)(3 * k)], c->ev[(size_t)(3 * k + 1)]));
+        HIPCHK(c, hipEventElapsedTime(&y, c->ev[(size_t)(3 * k + 1)], c->ev[(size_t)(3 * k + 2)]));
+        md += x; mw += y; ms += (double)x + (double)y;
     }
     if (launches) *launches = c->prof_launches;
     if (ms_total) *ms_total = ms;
+    c->prof_ms_dry = md;
+    c->prof_ms_step = mw;
     c->prof_launches = 0;
     return GF_OK;
 }

@@ -83,6 +83,9 @@ struct StepArgs {
     unsigned int *queue;         // next work item (persistent form); reset to 0 by the last workgroup
     int32_t persistent;          // 1: resident workgroups take items from the queue
     uint8_t *dry0, *dry1;        // per slot and buffer: 1 iff every interior cell has h <= tau
+    int32_t *wet_list;           // work items dry_kernel left for step_kernel
+    unsigned int *wet_count;     // their number; reset to 0 by the last workgroup of step_kernel
+    int32_t all_items;           // 1: step_kernel takes every work item (ghost fill)
     R *ghost_out;            // gf_fill_ghosts: [cap][4][(m+4)^2], else null
 };
 
@@ -100,6 +103,7 @@ struct RefluxArgsBase {
 #define GF_DECL_LAUNCHERS(SFX, R)                                                                  \
     hipError_t gf_launch_step_##SFX(const gf::StepArgs<R> &a, int m, int nt, int grid, hipStream_t s); \
     int gf_step_threads_ok_##SFX(int m, int nt);                                                   \
+    hipError_t gf_launch_dry_##SFX(const gf::StepArgs<R> &a, int m, hipStream_t s);                \
     int gf_step_resident_##SFX(int m, int nt);                                                     \
     hipError_t gf_launch_dryflag_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,     \
                                        const R *q0, const R *q1, uint8_t *f0, uint8_t *f1,         \

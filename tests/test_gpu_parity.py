@@ -218,6 +218,34 @@ def test_reservoir_fp64_parity(orc, m, level, sched):
     check_fp64(ctx.state(0), o.state(), f"reservoir m{m}")
 
 
+def test_autotune_leaves_state_unchanged(tmp_path):
+    """The tuner restores state, clocks and budgets after its trials: a tuned
+    context then steps to the same bits as an untuned one; a second call is
+    served from the cache."""
+    sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
+    ctxs = []
+    for tune in (False, True):
+        ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+        ctx.set_initial(0)
+        ctx.step(7)
+        if tune:
+            before = ctx.state(0), ctx.time(0), ctx.mass(0)
+            cache = str(tmp_path / "tune.txt")
+            nt, sched, us = ctx.autotune(steps=3, cache=cache)
+            assert nt in (64, 128, 256) and sched in (-1, 0) and us > 0
+            after = ctx.state(0), ctx.time(0), ctx.mass(0)
+            assert np.array_equal(before[0], after[0])
+            assert before[1] == after[1]
+            assert np.array_equal(before[2], after[2])
+            nt2, sched2, us2 = ctx.autotune(steps=3, cache=cache)
+            assert (nt2, sched2, us2) == (nt, sched, -1.0)
+            assert ctx.step_threads() == nt
+        ctx.step(20)
+        ctxs.append(ctx)
+    assert np.array_equal(ctxs[0].state(0), ctxs[1].state(0))
+    assert ctxs[0].time(0) == ctxs[1].time(0)
+
+
 def test_adaptive_step_controller(orc):
     """Library-chosen step lengths follow the same controller: first step from
     the speed pass, then dt cfl/nu, truncated at t_end."""
