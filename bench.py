@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 import numpy as np
 
 METRIC = "cell-updates/s and % HBM roofline, FP32-batched AMR vs FP64 plain, 1 MI355X"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_fp32_reservoir2048_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_fp32_reservoir2048_hbm_traffic.txt")
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"f32": 28.0, "f64": 56.0}
 
@@ -133,7 +133,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 run (0: the same as --steps)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--step-threads", type=int, default=0, help="step-kernel workgroup size (0: library default)")
+    ap.add_argument("--step-threads", type=int, default=0, help="step-kernel workgroup size (0: chosen by the tuner)")
+    ap.add_argument("--workload", choices=["reservoir", "wet"], default="reservoir",
+                    help="run only this grid (counter collection); the JSON line is for the reservoir")
     ap.add_argument("--wet-steps", type=int, default=200, help="steps of the all-wet comparison run (0: skip)")
     ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
                     help="run only one path (for counter collection); the JSON line needs both")
@@ -147,7 +149,7 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
     import paper_2403_15435_amd as gf
-    sc = workload()
+    sc = workload() if args.workload == "reservoir" else wet_workload()
     print(f"[bench] workload ready: {sc.name}, {4096} patches", file=sys.stderr, flush=True)
     nt = args.step_threads or None
     if args.fp64_steps <= 0:

@@ -218,6 +218,32 @@ def test_reservoir_fp64_parity(orc, m, level, sched):
     check_fp64(ctx.state(0), o.state(), f"reservoir m{m}")
 
 
+@pytest.mark.parametrize("sched", [-1, 4])
+def test_ensemble_in_one_launch(orc, sched):
+    """Uneven dam-break scenarios (different grid sizes, friction, breach
+    widths) advanced together: every step is one launch over all their
+    patches, each scenario keeps its own adaptive step, and each matches its
+    own oracle run bit for bit."""
+    scs = inputs.ensemble_dambreaks(n_scen=4, master_seed=4000, sizes=(64, 128, 256))
+    for sc in scs:
+        sc.t_end = 1e9
+    ctx = gf.Context(scs, precision=gf.GF_FP64, max_patches=256)
+    ctx.set_schedule(sched)
+    oracles = []
+    for k, sc in enumerate(scs):
+        o = orc.Oracle(sc)
+        init_oracle(o, sc)
+        ctx.set_state(k, o.state())
+        oracles.append(o)
+    st = ctx.step(25)
+    assert st.steps == 25 * len(scs)
+    for k, o in enumerate(oracles):
+        o.advance(25)
+        t, dt, steps, rej = ctx.time(k)
+        assert steps == o.steps and t == o.t and dt == o.dt, (k, t, o.t, dt, o.dt)
+        check_fp64(ctx.state(k), o.state(), f"ensemble member {k} ({scs[k].name})")
+
+
 def test_autotune_leaves_state_unchanged(tmp_path):
     """The tuner restores state, clocks and budgets after its trials: a tuned
     context then steps to the same bits as an untuned one; a second call is
