@@ -351,3 +351,24 @@ def ensemble_dambreaks(n_scen: int = 256, master_seed: int = 4000, m: int = 32,
         sc.eta_fn = eta
         out.append(sc)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Learned tagger: initial weights (drawn here once, passed to both sides)
+# ---------------------------------------------------------------------------
+CNN_PARAM_SHAPES = [("W1", (16, 3, 3, 4)), ("b1", (16,)), ("W2", (32, 3, 3, 16)), ("b2", (32,)),
+                    ("W3", (32, 3, 3, 32)), ("b3", (32,)), ("Wf", (3, 32)), ("bf", (3,))]
+
+
+def cnn_init_params(seed: int = 0) -> np.ndarray:
+    """He-normal initial weights (std sqrt(2 / fan_in)), zero biases, as one
+    float32-representable vector in the layout W1, b1, W2, b2, W3, b3, Wf, bf."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in CNN_PARAM_SHAPES:
+        if name.startswith("W"):
+            fan_in = int(np.prod(shape[1:]))
+            parts.append(rng.standard_normal(int(np.prod(shape))) * math.sqrt(2.0 / fan_in))
+        else:
+            parts.append(np.zeros(int(np.prod(shape))))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
