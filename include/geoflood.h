@@ -200,6 +200,45 @@ int gf_profile_enable(gf_ctx *ctx, int32_t on);
 int gf_profile_read(gf_ctx *ctx, int64_t *launches, double *ms_total);
 int gf_profile_split(gf_ctx *ctx, double *ms_dry, double *ms_step);
 
+/* ------------------------------------------------------------------------
+ * Learned refinement tagger (for callers that regrid less often than they
+ * tag): a small convolutional network predicts per patch whether the plain
+ * criteria of Section 4.1 will ask to refine (+1), keep (0) or coarsen (-1)
+ * it over the next steps.  Features of a leaf at level l: the 24 x 24
+ * pixels around it at its level (3 x 3 patch squares, 8 x 8 pixels each, a
+ * pixel the area mean over m/8 x m/8 cells of the leaf fields), channels
+ * h, hu/10, hv/10, (b - leaf mean b)/10, zero outside the domain; layout
+ * [y][x][channel].  Network: 3x3 convolutions 4->16 (stride 1), 16->32
+ * (stride 2), 32->32 (stride 2), ReLU after each, mean pooling, fully
+ * connected 32->3; BF16 matrix-core products, FP32 accumulation.
+ * ------------------------------------------------------------------------ */
+#define GF_NET_PARAMS 14579   /* W1[16][3][3][4] b1[16] W2[32][3][3][16] b2[32] W3[32][3][3][32] b3[32] Wf[3][32] bf[3] */
+#define GF_NET_FEATURES 2304  /* values per patch: 24 x 24 x 4 */
+
+/* Set the parameters (FP32 master copy; n must be GF_NET_PARAMS) and reset
+ * the optimiser.  Errors: GF_E_INVALID, GF_E_NOMEM. */
+int gf_net_set_params(gf_ctx *ctx, const double *params, int64_t n);
+int gf_net_get_params(gf_ctx *ctx, double *out, int64_t n);
+/* Feature tiles of every leaf of every scenario, in leaf order, from the
+ * current state: n_leaves x GF_NET_FEATURES values (out nullable to query
+ * the count; cap in values).  Errors: GF_E_STATE, GF_E_INVALID (cap),
+ * GF_E_UNSUPPORTED (feature images above 2^28 values). */
+int gf_net_features(gf_ctx *ctx, double *out, int64_t cap, int64_t *n_leaves);
+/* Logits (n x 3) for n feature tiles given on the host (rounded to BF16 on
+ * the device). */
+int gf_net_forward(gf_ctx *ctx, const double *x, int32_t n, double *logits);
+/* One training step on n samples: labels y in {0 coarsen, 1 keep, 2 refine},
+ * class weights class_w[3]; loss = sum over samples of
+ * class_w[y] (-log softmax[y]) / sum of class_w[y].  Writes the loss and, if
+ * grad is not null, the gradient before the Adam update (lr; beta1 0.9,
+ * beta2 0.999, eps 1e-8).  Errors: GF_E_STATE (no parameters), GF_E_INVALID. */
+int gf_net_train_step(gf_ctx *ctx, const double *x, const int8_t *y, int32_t n, const double *class_w, double lr,
+                      double *loss, double *grad);
+/* Flags from the network for every leaf (largest logit, kept within each
+ * scenario's level limits), in leaf order; they become the flags that
+ * gf_regrid(ctx, NULL, ...) applies, as after gf_tag. */
+int gf_net_predict(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
+
 /* Description of the last failure on this context (static storage, valid
  * until the next call on it). */
 const char *gf_last_error(const gf_ctx *ctx);

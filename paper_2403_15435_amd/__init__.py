@@ -41,10 +41,14 @@ class gf_step_stats(C.Structure):
                 ("t_min", C.c_double), ("t_max", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double)]
 
 
+NET_PARAMS = 14579
+NET_FEATURES = 2304
+
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step",
            "gf_tag", "gf_regrid", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
-           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_split", "gf_last_error", "gf_version"]
+           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_split", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
+           "gf_net_forward", "gf_net_train_step", "gf_net_predict", "gf_last_error", "gf_version"]
 
 _lib = None
 
@@ -89,6 +93,13 @@ def load(path: str = LIB_PATH):
     L.gf_profile_enable.argtypes = [vp, i32]
     L.gf_profile_read.argtypes = [vp, C.POINTER(i64), dp]
     L.gf_profile_split.argtypes = [vp, dp, dp]
+    i8p = C.POINTER(C.c_int8)
+    L.gf_net_set_params.argtypes = [vp, dp, i64]
+    L.gf_net_get_params.argtypes = [vp, dp, i64]
+    L.gf_net_features.argtypes = [vp, dp, i64, C.POINTER(i64)]
+    L.gf_net_forward.argtypes = [vp, dp, i32, dp]
+    L.gf_net_train_step.argtypes = [vp, dp, i8p, i32, dp, C.c_double, dp, dp]
+    L.gf_net_predict.argtypes = [vp, i8p, i64, C.POINTER(i64)]
     L.gf_last_error.argtypes = [vp]
     L.gf_last_error.restype = C.c_char_p
     L.gf_version.restype = C.c_char_p
@@ -288,6 +299,47 @@ class Context:
         n, ms = C.c_int64(), C.c_double()
         self._chk(self.L.gf_profile_read(self._p, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+    # --------------------------------------------------------- learned tagger
+    def net_set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        self._chk(self.L.gf_net_set_params(self._p, _dptr(p), p.size))
+
+    def net_params(self) -> np.ndarray:
+        out = np.zeros(NET_PARAMS)
+        self._chk(self.L.gf_net_get_params(self._p, _dptr(out), NET_PARAMS))
+        return out
+
+    def net_features(self) -> np.ndarray:
+        """(n_leaves, 24, 24, 4) feature tiles of all scenarios' leaves (FP32 values)."""
+        n = C.c_int64()
+        self._chk(self.L.gf_net_features(self._p, None, 0, C.byref(n)))
+        out = np.zeros((n.value, 24, 24, 4))
+        self._chk(self.L.gf_net_features(self._p, _dptr(out), out.size, C.byref(n)))
+        return out
+
+    def net_forward(self, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, NET_FEATURES)
+        out = np.zeros((x.shape[0], 3))
+        self._chk(self.L.gf_net_forward(self._p, _dptr(x), x.shape[0], _dptr(out)))
+        return out
+
+    def net_train_step(self, x: np.ndarray, y: np.ndarray, class_w, lr: float, want_grad: bool = False):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, NET_FEATURES)
+        y = np.ascontiguousarray(y, dtype=np.int8)
+        cw = np.ascontiguousarray(class_w, dtype=np.float64)
+        loss = C.c_double()
+        g = np.zeros(NET_PARAMS) if want_grad else None
+        self._chk(self.L.gf_net_train_step(self._p, _dptr(x), y.ctypes.data_as(C.POINTER(C.c_int8)), x.shape[0],
+                                           _dptr(cw), lr, C.byref(loss), _dptr(g) if want_grad else None))
+        return (loss.value, g) if want_grad else loss.value
+
+    def net_predict(self) -> np.ndarray:
+        n = C.c_int64()
+        cap = sum(self.leaves(k).shape[0] for k in range(len(self.scenarios)))
+        out = np.zeros(cap, dtype=np.int8)
+        self._chk(self.L.gf_net_predict(self._p, out.ctypes.data_as(C.POINTER(C.c_int8)), cap, C.byref(n)))
+        return out[:n.value]
 
     def profile_split(self):
         """(ms in the dry-patch kernel, ms in the full step kernel) of the last profile_read."""

@@ -19,6 +19,7 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall", "-Wno
 UNITS = [
     ("gf_kernels_f32.hip", ["-ffp-contract=fast"]),
     ("gf_kernels_f64.hip", ["-ffp-contract=off"]),
+    ("gf_net.hip", ["-ffp-contract=off"]),
     ("gf_host.cpp", ["-ffp-contract=off"]),
 ]
 

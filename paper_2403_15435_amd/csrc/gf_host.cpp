@@ -2,6 +2,7 @@
 // pool, halo descriptors, regrid topology and the C ABI (include/geoflood.h).
 #include "../../include/geoflood.h"
 #include "gf_internal.h"
+#include "gf_net.h"
 
 #include <algorithm>
 #include <cstdarg>
@@ -96,6 +97,26 @@ struct gf_ctx {
     int64_t prof_launches = 0;
     double prof_ms = 0.0;
     std::string err;
+    // learned tagger
+    struct Net {
+        float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+        uint16_t *wb = nullptr;
+        int64_t t = 0;
+        float *x = nullptr;                 // staged features [rows][FEAT]
+        int8_t *y = nullptr;
+        float *logits = nullptr, *loss = nullptr, *part = nullptr;
+        int64_t n_cap = 0;
+        float *featf = nullptr;
+        uint16_t *featb = nullptr;
+        int64_t feat_cap = 0;
+        float *img = nullptr;
+        size_t img_cap = 0;
+        int32_t *map = nullptr;
+        size_t map_cap = 0;
+        gfnet::FeatLevel *lv = nullptr;     // 16 levels
+        int32_t *lij = nullptr;
+        int64_t lij_cap = 0;
+    } net;
 };
 
 namespace {
@@ -535,6 +556,42 @@ void to_real(const double *in, R *out, size_t n) { for (size_t i = 0; i < n; ++i
 template <typename R>
 void from_real(const R *in, double *out, size_t n) { for (size_t i = 0; i < n; ++i) out[i] = (double)in[i]; }
 
+// device buffer of at least `need` elements (contents not kept)
+template <typename T>
+hipError_t grow(T **p, int64_t &cap, int64_t need)
+{
+    if (need <= cap && *p) return hipSuccess;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)std::max<int64_t>(need, 1));
+    if (e == hipSuccess) cap = need;
+    return e;
+}
+
+struct TuneKey {
+    std::string text;
+};
+
+TuneKey tune_key(const gf_ctx *c)
+{
+    int64_t n = (int64_t)c->desc.size();
+    int64_t bucket = 1;
+    while (bucket < n) bucket <<= 1;   // patch count rounded up to a power of two
+    char buf[160];
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    snprintf(buf, sizeof buf, "%s/%s/m%d/n%lld", arch.c_str(), c->prec == GF_FP32 ? "fp32" : "fp64", c->m,
+             (long long)bucket);
+    return TuneKey{buf};
+}
+
 }  // namespace
 
 // =========================================================================
@@ -637,6 +694,10 @@ void gf_destroy(gf_ctx *c)
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count};
     for (void *p : ps)
+        if (p) (void)hipFree(p);
+    void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
+                  c->net.part, c->net.featf, c->net.featb, c->net.img, c->net.map, c->net.lv, c->net.lij};
+    for (void *p : pn)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
@@ -1125,6 +1186,274 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
     return GF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// learned tagger
+// ---------------------------------------------------------------------------
+namespace {
+
+int net_ready(gf_ctx *c) { return c->net.w ? GF_OK : fail(c, GF_E_STATE, "network parameters not set"); }
+
+int net_stage_batch(gf_ctx *c, const double *x, int32_t n)
+{
+    auto &N = c->net;
+    if (n > N.n_cap) {
+        int64_t cap = N.n_cap;
+        int64_t c1 = cap, c2 = cap, c3 = cap, c4 = cap, c5 = cap;
+        hipError_t e = grow(&N.x, c1, (int64_t)n * gfnet::FEAT);
+        if (e == hipSuccess) e = grow(&N.y, c2, n);
+        if (e == hipSuccess) e = grow(&N.logits, c3, (int64_t)n * 3);
+        if (e == hipSuccess) e = grow(&N.loss, c4, n);
+        if (e == hipSuccess) e = grow(&N.part, c5, (int64_t)n * gfnet::N_PARAMS);
+        if (e != hipSuccess) { N.n_cap = 0; return fail(c, GF_E_NOMEM, "network batch buffers: %s", hipGetErrorString(e)); }
+        N.n_cap = n;
+    }
+    if (x) {
+        std::vector<float> xf((size_t)n * gfnet::FEAT);
+        for (size_t i = 0; i < xf.size(); ++i) xf[i] = (float)x[i];
+        HIPCHK(c, hipMemcpyAsync(N.x, xf.data(), sizeof(float) * xf.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return GF_OK;
+}
+
+// feature tiles of every leaf of every scenario (leaf order) into featf/featb
+int net_features(gf_ctx *c, int64_t *n_out)
+{
+    auto &N = c->net;
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    rc = pull_scen(c);
+    if (rc) return rc;
+    int64_t total = 0;
+    for (auto &s : c->sc) total += (int64_t)s.leaves.size();
+    int64_t cap1 = N.feat_cap, cap2 = N.feat_cap;
+    if (total > N.feat_cap) {
+        if (grow(&N.featf, cap1, total * gfnet::FEAT) != hipSuccess || grow(&N.featb, cap2, total * gfnet::FEAT) != hipSuccess)
+            return fail(c, GF_E_NOMEM, "feature buffers");
+        N.feat_cap = total;
+    }
+    if (!N.lv) HIPCHK(c, hipMalloc((void **)&N.lv, sizeof(gfnet::FeatLevel) * 16));
+    const int m = c->m;
+    int64_t row = 0;
+    for (size_t si = 0; si < c->sc.size(); ++si) {
+        const Scen &S = c->sc[si];
+        if (S.leaves.empty()) continue;
+        int Lf = 0;
+        for (const Leaf &L : S.leaves) Lf = std::max(Lf, L.level);
+        std::vector<gfnet::FeatLevel> lv((size_t)Lf + 1);
+        int64_t moff = 0, ioff = 0;
+        for (int l = 0; l <= Lf; ++l) {
+            lv[l].map_off = moff;
+            lv[l].map_w = S.d.mi << l;
+            moff += (int64_t)(S.d.mi << l) * (S.d.mj << l);
+            lv[l].img_off = ioff;
+            lv[l].nx = 8 * (S.d.mi << l);
+            lv[l].ny = 8 * (S.d.mj << l);
+            ioff += 4 * (int64_t)lv[l].nx * lv[l].ny;
+        }
+        if (ioff > ((int64_t)1 << 28)) return fail(c, GF_E_UNSUPPORTED, "feature images too large for level %d", Lf);
+        std::vector<int32_t> map((size_t)moff, -1);
+        std::vector<int32_t> lij(S.leaves.size() * 3);
+        for (size_t k = 0; k < S.leaves.size(); ++k) {
+            const Leaf &L = S.leaves[k];
+            map[(size_t)(lv[L.level].map_off + L.PJ * lv[L.level].map_w + L.PI)] = L.slot;
+            lij[3 * k] = L.level;
+            lij[3 * k + 1] = (int32_t)L.PI;
+            lij[3 * k + 2] = (int32_t)L.PJ;
+        }
+        int64_t mc = (int64_t)N.map_cap, ic = (int64_t)N.img_cap;
+        if (grow(&N.map, mc, moff) != hipSuccess || grow(&N.img, ic, ioff) != hipSuccess)
+            return fail(c, GF_E_NOMEM, "feature images");
+        N.map_cap = (size_t)mc;
+        N.img_cap = (size_t)ic;
+        if (grow(&N.lij, N.lij_cap, (int64_t)lij.size()) != hipSuccess) return fail(c, GF_E_NOMEM, "leaf table");
+        HIPCHK(c, hipMemcpyAsync(N.map, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(N.lv, lv.data(), sizeof(gfnet::FeatLevel) * lv.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(N.lij, lij.data(), sizeof(int32_t) * lij.size(), hipMemcpyHostToDevice, c->stream));
+        const int cur = c->hs[si].cur;
+        hipError_t e;
+        if (c->prec == GF_FP32)
+            e = gfnet_launch_image_f32((const float *)c->q[cur], (const float *)c->b, c->cap, m, N.map, N.lv, lv[Lf], Lf,
+                                       N.img, c->stream);
+        else
+            e = gfnet_launch_image_f64((const double *)c->q[cur], (const double *)c->b, c->cap, m, N.map, N.lv, lv[Lf],
+                                       Lf, N.img, c->stream);
+        for (int l = Lf - 1; l >= 0 && e == hipSuccess; --l)
+            e = gfnet_launch_pyramid(N.img + lv[l + 1].img_off, lv[l + 1].nx, lv[l + 1].ny, N.img + lv[l].img_off,
+                                     lv[l].nx, lv[l].ny, c->stream);
+        if (e == hipSuccess)
+            e = gfnet_launch_tiles(N.img, N.lv, N.lij, (int)S.leaves.size(), N.featf + row * gfnet::FEAT,
+                                   N.featb + row * gfnet::FEAT, c->stream);
+        if (e != hipSuccess) return fail(c, GF_E_HIP, "feature launch: %s", hipGetErrorString(e));
+        HIPCHK(c, hipStreamSynchronize(c->stream));   // the staging tables are reused by the next scenario
+        row += (int64_t)S.leaves.size();
+    }
+    if (n_out) *n_out = total;
+    return GF_OK;
+}
+
+}  // namespace
+
+int gf_net_set_params(gf_ctx *c, const double *params, int64_t n)
+{
+    if (!c || !params || n != gfnet::N_PARAMS) return GF_E_INVALID;
+    auto &N = c->net;
+    if (!N.w) {
+        size_t b = sizeof(float) * gfnet::N_PARAMS;
+        if (hipMalloc((void **)&N.w, b) != hipSuccess || hipMalloc((void **)&N.m, b) != hipSuccess ||
+            hipMalloc((void **)&N.v, b) != hipSuccess || hipMalloc((void **)&N.g, b) != hipSuccess ||
+            hipMalloc((void **)&N.wb, sizeof(uint16_t) * gfnet::N_PARAMS) != hipSuccess)
+            return fail(c, GF_E_NOMEM, "network parameters");
+    }
+    std::vector<float> w((size_t)n);
+    for (int64_t i = 0; i < n; ++i) w[(size_t)i] = (float)params[i];
+    HIPCHK(c, hipMemcpyAsync(N.w, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(N.m, 0, sizeof(float) * w.size(), c->stream));
+    HIPCHK(c, hipMemsetAsync(N.v, 0, sizeof(float) * w.size(), c->stream));
+    hipError_t e = gfnet_launch_to_bf16(N.w, N.wb, gfnet::N_PARAMS, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "weight conversion: %s", hipGetErrorString(e));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    N.t = 0;
+    return GF_OK;
+}
+
+int gf_net_get_params(gf_ctx *c, double *out, int64_t n)
+{
+    if (!c || !out || n != gfnet::N_PARAMS) return GF_E_INVALID;
+    int rc = net_ready(c);
+    if (rc) return rc;
+    std::vector<float> w((size_t)n);
+    HIPCHK(c, hipMemcpyAsync(w.data(), c->net.w, sizeof(float) * w.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i) out[i] = w[(size_t)i];
+    return GF_OK;
+}
+
+int gf_net_features(gf_ctx *c, double *out, int64_t cap, int64_t *n_leaves)
+{
+    if (!c) return GF_E_INVALID;
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int64_t n = 0;
+    int rc = net_features(c, &n);
+    if (rc) return rc;
+    if (n_leaves) *n_leaves = n;
+    if (!out) return GF_OK;
+    if (cap < n * gfnet::FEAT) return fail(c, GF_E_INVALID, "feature buffer too small");
+    std::vector<float> f((size_t)(n * gfnet::FEAT));
+    HIPCHK(c, hipMemcpyAsync(f.data(), c->net.featf, sizeof(float) * f.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < f.size(); ++i) out[i] = f[i];
+    return GF_OK;
+}
+
+int gf_net_forward(gf_ctx *c, const double *x, int32_t n, double *logits)
+{
+    if (!c || !x || !logits || n <= 0) return GF_E_INVALID;
+    int rc = net_ready(c);
+    if (rc) return rc;
+    rc = net_stage_batch(c, x, n);
+    if (rc) return rc;
+    auto &N = c->net;
+    gfnet::NetArgs a{};
+    a.x = N.x; a.n = n; a.w = N.w; a.wb = N.wb; a.logits = N.logits;
+    hipError_t e = gfnet_launch_forward(a, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "network launch: %s", hipGetErrorString(e));
+    std::vector<float> z((size_t)n * 3);
+    HIPCHK(c, hipMemcpyAsync(z.data(), N.logits, sizeof(float) * z.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < z.size(); ++i) logits[i] = z[i];
+    return GF_OK;
+}
+
+int gf_net_train_step(gf_ctx *c, const double *x, const int8_t *y, int32_t n, const double *class_w, double lr,
+                      double *loss, double *grad)
+{
+    if (!c || !x || !y || !class_w || n <= 0 || !(lr >= 0.0)) return GF_E_INVALID;
+    int rc = net_ready(c);
+    if (rc) return rc;
+    double wtot = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (y[i] < 0 || y[i] > 2) return fail(c, GF_E_INVALID, "class label out of range");
+        wtot += class_w[y[i]];
+    }
+    if (!(wtot > 0.0)) return fail(c, GF_E_INVALID, "class weights sum to zero over the batch");
+    rc = net_stage_batch(c, x, n);
+    if (rc) return rc;
+    auto &N = c->net;
+    HIPCHK(c, hipMemcpyAsync(N.y, y, (size_t)n, hipMemcpyHostToDevice, c->stream));
+    gfnet::NetArgs a{};
+    a.x = N.x; a.n = n; a.w = N.w; a.wb = N.wb; a.logits = N.logits;
+    a.y = N.y; a.cw[0] = (float)class_w[0]; a.cw[1] = (float)class_w[1]; a.cw[2] = (float)class_w[2];
+    a.wtot = (float)wtot; a.loss_i = N.loss; a.part = N.part;
+    hipError_t e = gfnet_launch_train(a, c->stream);
+    if (e == hipSuccess) e = gfnet_launch_reduce(N.part, n, N.g, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "training launch: %s", hipGetErrorString(e));
+    if (grad) {
+        std::vector<float> g(gfnet::N_PARAMS);
+        HIPCHK(c, hipMemcpyAsync(g.data(), N.g, sizeof(float) * g.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < g.size(); ++i) grad[i] = g[i];
+    }
+    N.t += 1;
+    const double bc1 = 1.0 - std::pow(0.9, (double)N.t), bc2 = 1.0 - std::pow(0.999, (double)N.t);
+    e = gfnet_launch_adam(N.w, N.m, N.v, N.wb, N.g, (float)lr, (float)bc1, (float)bc2, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "optimiser launch: %s", hipGetErrorString(e));
+    if (loss) {
+        std::vector<float> li((size_t)n);
+        HIPCHK(c, hipMemcpyAsync(li.data(), N.loss, sizeof(float) * li.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double L = 0.0;
+        for (float v : li) L += v;
+        *loss = L;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int gf_net_predict(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n_out)
+{
+    if (!c) return GF_E_INVALID;
+    int rc = net_ready(c);
+    if (rc) return rc;
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int64_t n = 0;
+    rc = net_features(c, &n);
+    if (rc) return rc;
+    rc = net_stage_batch(c, nullptr, (int32_t)n);
+    if (rc) return rc;
+    auto &N = c->net;
+    gfnet::NetArgs a{};
+    a.x = nullptr; a.xb = N.featb; a.n = (int)n; a.w = N.w; a.wb = N.wb; a.logits = N.logits;
+    hipError_t e = gfnet_launch_forward(a, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "network launch: %s", hipGetErrorString(e));
+    std::vector<float> z((size_t)n * 3);
+    HIPCHK(c, hipMemcpyAsync(z.data(), N.logits, sizeof(float) * z.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // largest logit -> flag, within the scenario's level limits
+    std::vector<int8_t> flags((size_t)n);
+    int64_t k = 0;
+    for (auto &S : c->sc)
+        for (const Leaf &L : S.leaves) {
+            const float *zz = &z[(size_t)(3 * k)];
+            int cls = 1;
+            if (zz[0] > zz[cls]) cls = 0;
+            if (zz[2] > zz[cls]) cls = 2;
+            int8_t f = (int8_t)(cls - 1);
+            if (f > 0 && L.level >= S.d.max_level) f = 0;
+            if (f < 0 && L.level <= S.d.min_level) f = 0;
+            flags[(size_t)k++] = f;
+        }
+    c->last_flags = flags;
+    if (n_out) *n_out = n;
+    if (flags_out) {
+        if (cap < n) return fail(c, GF_E_INVALID, "flag buffer too small");
+        std::memcpy(flags_out, flags.data(), (size_t)n);
+    }
+    return GF_OK;
+}
+
 int gf_mass(gf_ctx *c, int32_t scen, double *mass, double *clamp_volume, double *boundary_volume)
 {
     int rc = check_scen(c, scen);
@@ -1209,29 +1538,6 @@ int gf_get_step_threads(gf_ctx *c, int32_t *nt)
 // every trial, so tuning does not change the simulation.
 // ---------------------------------------------------------------------------
 namespace {
-
-struct TuneKey {
-    std::string text;
-};
-
-TuneKey tune_key(const gf_ctx *c)
-{
-    int64_t n = (int64_t)c->desc.size();
-    int64_t bucket = 1;
-    while (bucket < n) bucket <<= 1;   // patch count rounded up to a power of two
-    char buf[160];
-    hipDeviceProp_t prop{};
-    int dev = 0;
-    std::string arch = "unknown";
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
-        arch = prop.gcnArchName;
-        const size_t colon = arch.find(':');
-        if (colon != std::string::npos) arch = arch.substr(0, colon);
-    }
-    snprintf(buf, sizeof buf, "%s/%s/m%d/n%lld", arch.c_str(), c->prec == GF_FP32 ? "fp32" : "fp64", c->m,
-             (long long)bucket);
-    return TuneKey{buf};
-}
 
 // cache file: one line per key, "key threads sched us_per_step"
 bool cache_lookup(const char *path, const std::string &key, int *nt, int *sched)
