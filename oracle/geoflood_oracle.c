@@ -1217,7 +1217,12 @@ static void clamp_leaf(orc_sim *s, leaf_t *L)
 }
 
 /* ------------------------------------------------------------------------ */
-/* refluxing at coarse/fine faces (reading R17)                              */
+/* refluxing at coarse/fine faces (reading R17'): the coarse cell's depth is  */
+/* corrected to the fine side's volume flux, so volume is conserved exactly; */
+/* its momentum is rescaled with the depth (velocity kept), zero if the cell */
+/* was dry or ends dry.  Correcting momentum by the fluctuation difference  */
+/* instead charged thin coarse cells with the fine side's pressure and bed   */
+/* terms and made rough-bed AMR runs unstable.                               */
 /* ------------------------------------------------------------------------ */
 
 static void reflux_all(orc_sim *s)
@@ -1260,8 +1265,21 @@ static void reflux_all(orc_sim *s)
                 else if (f == 1) { ci = m - 1; cj = kk; }
                 else if (f == 2) { ci = kk; cj = 0; }
                 else { ci = kk; cj = m - 1; }
-                for (q = 0; q < 3; ++q)
-                    C->q[q][G(s, ci, cj)] += (-gf[q] - C->gainC[(f * m + kk) * 3 + q]) / area;
+                {
+                    /* the depth takes the fine side's flux (volume is exact);
+                       the momentum follows at the cell's own velocity */
+                    const int gi = G(s, ci, cj);
+                    const double h0 = C->q[0][gi];
+                    const double h1 = h0 + (-gf[0] - C->gainC[(f * m + kk) * 3 + 0]) / area;
+                    C->q[0][gi] = h1;
+                    if (wet(s, h0) && h1 > 0.0) {
+                        C->q[1][gi] = C->q[1][gi] * (h1 / h0);
+                        C->q[2][gi] = C->q[2][gi] * (h1 / h0);
+                    } else {
+                        C->q[1][gi] = 0.0;
+                        C->q[2][gi] = 0.0;
+                    }
+                }
             }
         }
         if (touched) clamp_leaf(s, C);
