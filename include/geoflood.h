@@ -239,6 +239,39 @@ int gf_net_train_step(gf_ctx *ctx, const double *x, const int8_t *y, int32_t n, 
  * gf_regrid(ctx, NULL, ...) applies, as after gf_tag. */
 int gf_net_predict(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
 
+/* One collection window for training the tagger: the feature tiles of the
+ * current leaves (n x GF_NET_FEATURES, nullable), then `window` steps with
+ * the plain tagger run every `check_every` steps on this leaf set, labels
+ * (n, nullable) 2 (refine) if any check asked to refine, 0 (coarsen) if
+ * every check asked to coarsen, else 1; then a regrid with those flags.
+ * cap counts leaves: features holds cap x GF_NET_FEATURES values, labels
+ * cap entries (GF_E_INVALID if n exceeds it; *n is set either way).  window
+ * must be a multiple of check_every. */
+int gf_net_collect(gf_ctx *ctx, int32_t window, int32_t check_every, double *features, int8_t *labels, int64_t cap,
+                   int64_t *n);
+
+/* Adaptive run: `nsteps` steps with regridding.
+ *   GF_RUN_PLAIN:   plain tagger and regrid every check_every steps;
+ *   GF_RUN_SPARSE:  plain tagger and regrid every regrid_every steps; the
+ *                   plain tagger also runs at the checks between (counted
+ *                   as misses when it asks to refine, nothing done);
+ *   GF_RUN_LEARNED: network flags every regrid_every steps, with every plain
+ *                   refine request honoured and coarsening only where the
+ *                   plain tagger agrees; at the checks between, a plain
+ *                   refine request forces a regrid of those leaves.
+ * regrid_every must be a multiple of check_every. */
+enum { GF_RUN_PLAIN = 0, GF_RUN_SPARSE = 1, GF_RUN_LEARNED = 2 };
+typedef struct {
+    int64_t steps;           /* steps taken */
+    int64_t regrids;         /* scheduled regrids */
+    int64_t forced_regrids;  /* extra regrids forced by the checks (learned mode) */
+    int64_t checks;          /* leaves examined at checks */
+    int64_t misses;          /* of those, leaves the plain tagger wanted refined */
+    int64_t leaf_steps;      /* sum over steps of the leaf count (work) */
+    double seconds;          /* wall time of the call */
+} gf_run_stats;
+int gf_run(gf_ctx *ctx, int32_t nsteps, int32_t mode, int32_t check_every, int32_t regrid_every, gf_run_stats *stats);
+
 /* Description of the last failure on this context (static storage, valid
  * until the next call on it). */
 const char *gf_last_error(const gf_ctx *ctx);

@@ -41,6 +41,12 @@ class gf_step_stats(C.Structure):
                 ("t_min", C.c_double), ("t_max", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double)]
 
 
+class gf_run_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("regrids", C.c_int64), ("forced_regrids", C.c_int64), ("checks", C.c_int64),
+                ("misses", C.c_int64), ("leaf_steps", C.c_int64), ("seconds", C.c_double)]
+
+
+GF_RUN_PLAIN, GF_RUN_SPARSE, GF_RUN_LEARNED = 0, 1, 2
 NET_PARAMS = 14579
 NET_FEATURES = 2304
 
@@ -48,7 +54,7 @@ EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step",
            "gf_tag", "gf_regrid", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
            "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_split", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
-           "gf_net_forward", "gf_net_train_step", "gf_net_predict", "gf_last_error", "gf_version"]
+           "gf_net_forward", "gf_net_train_step", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
 
 _lib = None
 
@@ -100,6 +106,8 @@ def load(path: str = LIB_PATH):
     L.gf_net_forward.argtypes = [vp, dp, i32, dp]
     L.gf_net_train_step.argtypes = [vp, dp, i8p, i32, dp, C.c_double, dp, dp]
     L.gf_net_predict.argtypes = [vp, i8p, i64, C.POINTER(i64)]
+    L.gf_net_collect.argtypes = [vp, i32, i32, dp, i8p, i64, C.POINTER(i64)]
+    L.gf_run.argtypes = [vp, i32, i32, i32, i32, C.POINTER(gf_run_stats)]
     L.gf_last_error.argtypes = [vp]
     L.gf_last_error.restype = C.c_char_p
     L.gf_version.restype = C.c_char_p
@@ -340,6 +348,21 @@ class Context:
         out = np.zeros(cap, dtype=np.int8)
         self._chk(self.L.gf_net_predict(self._p, out.ctypes.data_as(C.POINTER(C.c_int8)), cap, C.byref(n)))
         return out[:n.value]
+
+    def net_collect(self, window: int = 16, check_every: int = 4):
+        """Features and labels (class 0 coarsen, 1 keep, 2 refine) of one window; regrids after it."""
+        n = C.c_int64()
+        cap = sum(self.leaves(k).shape[0] for k in range(len(self.scenarios)))
+        F = np.zeros((cap, 24, 24, 4))
+        y = np.zeros(cap, dtype=np.int8)
+        self._chk(self.L.gf_net_collect(self._p, window, check_every, _dptr(F), y.ctypes.data_as(C.POINTER(C.c_int8)),
+                                        cap, C.byref(n)))
+        return F[:n.value], y[:n.value].copy()
+
+    def run(self, nsteps: int, mode: int, check_every: int = 4, regrid_every: int = 16) -> "gf_run_stats":
+        st = gf_run_stats()
+        self._chk(self.L.gf_run(self._p, nsteps, mode, check_every, regrid_every, C.byref(st)))
+        return st
 
     def profile_split(self):
         """(ms in the dry-patch kernel, ms in the full step kernel) of the last profile_read."""

@@ -5,6 +5,7 @@
 #include "gf_net.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -1452,6 +1453,111 @@ int gf_net_predict(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n_out)
         std::memcpy(flags_out, flags.data(), (size_t)n);
     }
     return GF_OK;
+}
+
+int gf_net_collect(gf_ctx *c, int32_t window, int32_t check_every, double *features, int8_t *labels, int64_t cap,
+                   int64_t *n_out)
+{
+    if (!c || window <= 0 || check_every <= 0 || window % check_every) return GF_E_INVALID;
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int64_t n = 0;
+    int rc = net_features(c, &n);
+    if (rc) return rc;
+    if (n_out) *n_out = n;
+    if ((features || labels) && cap < n) return fail(c, GF_E_INVALID, "collect buffers too small (cap counts leaves)");
+    if (features) {
+        std::vector<float> f((size_t)(n * gfnet::FEAT));
+        HIPCHK(c, hipMemcpyAsync(f.data(), c->net.featf, sizeof(float) * f.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < f.size(); ++i) features[i] = f[i];
+    }
+    // plain-tagger checks over the window on this leaf set
+    std::vector<int8_t> any_refine((size_t)n, 0), all_coarsen((size_t)n, 1), fl((size_t)n);
+    for (int32_t k = check_every; k <= window; k += check_every) {
+        rc = gf_step(c, check_every, nullptr, nullptr);
+        if (rc) return rc;
+        int64_t nn = 0;
+        rc = gf_tag(c, fl.data(), n, &nn);
+        if (rc) return rc;
+        if (nn != n) return fail(c, GF_E_STATE, "leaf set changed during a collection window");
+        for (int64_t i = 0; i < n; ++i) {
+            any_refine[(size_t)i] |= fl[(size_t)i] > 0;
+            all_coarsen[(size_t)i] &= fl[(size_t)i] < 0;
+        }
+    }
+    std::vector<int8_t> lab((size_t)n);
+    for (int64_t i = 0; i < n; ++i) lab[(size_t)i] = any_refine[(size_t)i] ? 1 : (all_coarsen[(size_t)i] ? -1 : 0);
+    if (labels)
+        for (int64_t i = 0; i < n; ++i) labels[i] = (int8_t)(lab[(size_t)i] + 1);
+    int64_t nl = 0;
+    return gf_regrid(c, lab.data(), &nl);
+}
+
+int gf_run(gf_ctx *c, int32_t nsteps, int32_t mode, int32_t check_every, int32_t regrid_every, gf_run_stats *out)
+{
+    if (!c || nsteps < 0 || check_every <= 0 || (mode != GF_RUN_PLAIN && (regrid_every <= 0 || regrid_every % check_every)))
+        return GF_E_INVALID;
+    if (mode < GF_RUN_PLAIN || mode > GF_RUN_LEARNED) return GF_E_INVALID;
+    if (mode == GF_RUN_LEARNED) {
+        int rc = net_ready(c);
+        if (rc) return rc;
+    }
+    gf_run_stats st{};
+    const auto t0 = std::chrono::steady_clock::now();
+    auto n_leaves = [&]() {
+        int64_t n = 0;
+        for (auto &s : c->sc) n += (int64_t)s.leaves.size();
+        return n;
+    };
+    std::vector<int8_t> plain, learned;
+    int rc = GF_OK;
+    for (int32_t k = 0; k < nsteps && rc == GF_OK; k += check_every) {
+        const bool regrid_step = mode == GF_RUN_PLAIN || k % regrid_every == 0;
+        int64_t n = n_leaves(), nn = 0;
+        plain.resize((size_t)n);
+        rc = gf_tag(c, plain.data(), n, &nn);
+        if (rc) break;
+        if (regrid_step) {
+            if (mode == GF_RUN_LEARNED) {
+                learned.resize((size_t)n);
+                rc = gf_net_predict(c, learned.data(), n, &nn);
+                if (rc) break;
+                // the plain tagger stays the judge: its refine requests always
+                // hold, and a coarsening needs its agreement
+                for (int64_t i = 0; i < n; ++i) {
+                    int8_t f = learned[(size_t)i];
+                    if (plain[(size_t)i] > 0) f = 1;
+                    else if (f < 0 && plain[(size_t)i] >= 0) f = 0;
+                    learned[(size_t)i] = f;
+                }
+                rc = gf_regrid(c, learned.data(), &nn);
+            } else {
+                rc = gf_regrid(c, plain.data(), &nn);
+            }
+            st.regrids += 1;
+        } else {
+            int64_t miss = 0;
+            for (int64_t i = 0; i < n; ++i) miss += plain[(size_t)i] > 0;
+            st.checks += n;
+            st.misses += miss;
+            if (miss && mode == GF_RUN_LEARNED) {
+                for (auto &f : plain) f = f > 0 ? 1 : 0;
+                rc = gf_regrid(c, plain.data(), &nn);
+                st.forced_regrids += 1;
+            }
+        }
+        if (rc) break;
+        const int32_t ns = std::min(check_every, nsteps - k);
+        gf_step_stats ss{};
+        rc = gf_step(c, ns, nullptr, &ss);
+        st.steps += ns;
+        st.leaf_steps += n_leaves() * ns;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (out) *out = st;
+    return rc;
 }
 
 int gf_mass(gf_ctx *c, int32_t scen, double *mass, double *clamp_volume, double *boundary_volume)

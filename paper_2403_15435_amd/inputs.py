@@ -222,9 +222,10 @@ def ritter_dambreak(n_cells: int = 128, m: int = 16, h0: float = 10.0) -> Scenar
 
 def reservoir_fractal(level: int = 6, m: int = 32, seed: int = 2, radius: float = 400.0,
                       h_res: float = 20.0, L: float = 10000.0, manning_n: float = 0.033,
-                      dem_level: Optional[int] = None) -> Scenario:
+                      dem_level: Optional[int] = None, centre: Optional[Tuple[float, float]] = None) -> Scenario:
     """Square L x L domain, uniform level, fractal terrain 100 +/- 50 m, a
-    circular reservoir of depth h_res (h = 20 m for r <= radius, else dry)."""
+    circular reservoir of depth h_res (h = 20 m for r <= radius, else dry)
+    centred at `centre` (default: the domain centre)."""
     if dem_level is None:
         dem_level = level
     sc = Scenario(name=f"reservoir_l{level}_m{m}", x0=0.0, y0=0.0, x1=L, y1=L, mi=1, mj=1, m=m,
@@ -232,12 +233,24 @@ def reservoir_fractal(level: int = 6, m: int = 32, seed: int = 2, radius: float 
     nn = m * (1 << dem_level) + 1
     sc.dem = fractal_dem_nodes(nn, nn, L, L, seed, base=100.0, amp=50.0, norm="max")
     sc.dem_level = dem_level
-    cx = cy = 0.5 * L
+    cx, cy = (0.5 * L, 0.5 * L) if centre is None else centre
 
     def eta(X, Y, b):
         r = np.hypot(X - cx, Y - cy)
         return np.where(r <= radius, b + h_res, -1e9)
     sc.eta_fn = eta
+    return sc
+
+
+def adaptive_reservoir(seed: int, L: float = 4000.0, m: int = 16, max_level: int = 3, dem_level: int = 3,
+                       radius: float = 250.0) -> Scenario:
+    """The reservoir on AMR levels 0..max_level with its centre drawn from
+    U[L/4, 3L/4]^2 by the seed (the learned-tagger workload, scaled)."""
+    rng = np.random.default_rng(seed)
+    c = (float(rng.uniform(0.25 * L, 0.75 * L)), float(rng.uniform(0.25 * L, 0.75 * L)))
+    sc = reservoir_fractal(level=max_level, m=m, L=L, seed=seed, radius=radius, dem_level=dem_level, centre=c)
+    sc.name = f"adaptive_reservoir_{seed}"
+    sc.min_level, sc.max_level, sc.init_level = 0, max_level, 1
     return sc
 
 

@@ -88,48 +88,131 @@ def test_adam_step_and_training():
     assert losses[-1] < 0.5 * losses[0]
 
 
-def test_features_match_oracle():
-    """Feature tiles of an AMR mesh (levels 1-3) from the library's own state."""
-    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
-    sc.min_level, sc.max_level = 1, 3
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _amr_leaves():
     lv = [(0, 1, 0, 0), (0, 1, 1, 1)]
     lv += [(0, 2, 2 + a, b) for b in range(2) for a in range(2)]
     lv += [(0, 2, 0, 2), (0, 2, 1, 2), (0, 2, 1, 3)]
     lv += [(0, 3, a, 6 + b) for b in range(2) for a in range(2)]
-    leaves = np.array(lv, np.int32)
+    return np.array(lv, np.int32)
+
+
+def _oracle_state(orc, sc, leaves, steps):
+    """A state produced by the CPU solver oracle (never by the library)."""
+    from helpers import init_oracle
+    o = orc.Oracle(sc, leaves=leaves)
+    init_oracle(o, sc)
+    if steps:
+        o.advance(steps)
+    return o.leaves(), o.state()
+
+
+def test_features_match_oracle(orc):
+    """Feature tiles of an AMR mesh (levels 1-3): the library given the solver
+    oracle's state against the network oracle on that same state."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+    sc.min_level, sc.max_level = 1, 3
+    lv, st = _oracle_state(orc, sc, _amr_leaves(), 10)
     for prec in (gf.GF_FP32, gf.GF_FP64):
         ctx = gf.Context([sc], precision=prec, max_patches=64)
-        ctx.set_leaves(0, leaves)
-        ctx.set_initial(0)
-        ctx.step(10)
+        ctx.set_leaves(0, lv)
+        ref = st if prec == gf.GF_FP64 else st.astype(np.float32).astype(np.float64)
+        ctx.set_state(0, ref[:, :3])
+        assert np.array_equal(ctx.leaves(0), lv)
         Fg = ctx.net_features()
-        Fo = cn.features(sc, ctx.leaves(0), ctx.state(0))
+        Fo = cn.features(sc, lv, ref)
         err = np.abs(Fg - Fo).max()
         print(f"features ({'fp32' if prec == gf.GF_FP32 else 'fp64'} state): max abs diff {err:.2e}, "
               f"max value {np.abs(Fo).max():.2f}", flush=True)
         assert err <= 1e-5 * max(1.0, np.abs(Fo).max())
 
 
-def test_predict_flags_drive_regrid():
-    """Flags from the network stay within the level limits and are what a
-    following regrid applies."""
+def test_predict_flags_drive_regrid(orc):
+    """Flags from the network stay within the level limits, follow the oracle's
+    network on the oracle's features, and are what a following regrid applies."""
     sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
     sc.min_level, sc.max_level = 1, 3
-    ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=256)
-    ctx.set_initial(0)
+    lv, st = _oracle_state(orc, sc, sc.uniform_leaves(2), 0)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=256)
+    ctx.set_state(0, st[:, :3])
     params = inputs.cnn_init_params(8)
     params[cn.N_PARAMS - 3:] = [0.0, -5.0, 5.0]     # bias every leaf towards "refine"
     ctx.net_set_params(params)
-    lv = ctx.leaves(0)
     flags = ctx.net_predict()
     assert flags.shape == (lv.shape[0],)
     assert np.all(flags[lv[:, 1] >= sc.max_level] <= 0)
     assert np.all(flags[lv[:, 1] <= sc.min_level] >= 0)
-    F = ctx.net_features()
-    Z, _ = cn.forward(params, F, emulate=True)
+    Z, _ = cn.forward(params, cn.features(sc, lv, st), emulate=True)
     want = np.argmax(Z, axis=1) - 1
     want = np.where((want > 0) & (lv[:, 1] >= sc.max_level), 0, want)
     want = np.where((want < 0) & (lv[:, 1] <= sc.min_level), 0, want)
     assert np.mean(flags == want) >= 0.95
     n = ctx.regrid(None)
     assert n > lv.shape[0]
+
+
+def _adaptive_ctx(seed):
+    """The adaptive reservoir refined around its water by the plain tagger, the
+    initial state re-evaluated on each new mesh."""
+    sc = inputs.adaptive_reservoir(seed)
+    ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=1024)
+    ctx.set_initial(0)
+    for _ in range(sc.max_level):
+        ctx.regrid(ctx.tag())
+        ctx.set_initial(0)
+    return sc, ctx
+
+
+def test_learned_tagger_gain():
+    """Trained on the GPU from plain-tagger windows of four seeded runs, the
+    network anticipates refinement on an unseen run: regridding every 16 steps
+    with it misses fewer refine requests at the 4-step checks than regridding
+    every 16 steps without it, and needs fewer regrids than the plain tagger
+    every 4 steps, which stays the judge."""
+    from helpers import to_finest
+    X, Y = [], []
+    for seed in (5001, 5002, 5003, 5004):
+        sc, ctx = _adaptive_ctx(seed)
+        for _ in range(12):
+            F, y = ctx.net_collect(16, 4)
+            X.append(F)
+            Y.append(y)
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    counts = np.bincount(Y, minlength=3)
+    cw = counts.sum() / (3.0 * np.maximum(counts, 1))
+    print(f"training samples {len(Y)}, classes (coarsen, keep, refine) {counts.tolist()}", flush=True)
+    sc, ctx = _adaptive_ctx(5051)
+    ctx.net_set_params(inputs.cnn_init_params(0))
+    rng = np.random.default_rng(0)
+    losses = []
+    for it in range(300):
+        idx = rng.choice(len(Y), size=min(256, len(Y)), replace=False)
+        losses.append(ctx.net_train_step(X[idx], Y[idx], cw, lr=3e-3))
+    print(f"training loss {np.mean(losses[:10]):.3f} -> {np.mean(losses[-10:]):.3f}", flush=True)
+    assert np.mean(losses[-10:]) < 0.8 * np.mean(losses[:10])
+    params = ctx.net_params()
+    res = {}
+    for mode in (gf.GF_RUN_PLAIN, gf.GF_RUN_SPARSE, gf.GF_RUN_LEARNED):
+        sc, c2 = _adaptive_ctx(5051)
+        c2.net_set_params(params)
+        m0 = c2.mass(0)
+        st = c2.run(160, mode)
+        M = c2.mass(0)
+        assert abs((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) <= 1e-6 * m0[0]
+        res[mode] = (st, to_finest(sc, c2.leaves(0), c2.state(0), 0, sc.max_level))
+    hp = res[gf.GF_RUN_PLAIN][1]
+    for mode, name in ((gf.GF_RUN_PLAIN, "plain/4"), (gf.GF_RUN_SPARSE, "plain/16"), (gf.GF_RUN_LEARNED, "learned/16")):
+        st, h = res[mode]
+        rate = st.misses / max(st.checks, 1)
+        print(f"{name:10s}: regrids {st.regrids} + forced {st.forced_regrids}, misses {st.misses}/{st.checks} "
+              f"({rate:.3%}), leaf-steps {st.leaf_steps}, {st.seconds:.2f} s, "
+              f"max|h - h_plain| {np.abs(h - hp).max():.3e} m", flush=True)
+    sp, le, pl = res[gf.GF_RUN_SPARSE][0], res[gf.GF_RUN_LEARNED][0], res[gf.GF_RUN_PLAIN][0]
+    assert le.misses < sp.misses
+    assert le.regrids + le.forced_regrids < pl.regrids

@@ -422,8 +422,15 @@ def test_tag_and_regrid_bit_exact(orc, prec):
     init_oracle(o, sc, "f32" if prec == gf.GF_FP32 else "f64")
     ctx = gf.Context([sc], precision=prec, max_patches=400)
     gpu_init_like(ctx, o, "f32" if prec == gf.GF_FP32 else "f64")
-    m0 = ctx.mass(0)[0]
+    base = ctx.mass(0)
     for cycle in range(3):
+        if prec == gf.GF_FP32 and cycle > 0:
+            # the FP32 data decides the flags: both sides take the oracle's own
+            # state rounded to FP32 (the volume budget restarts there)
+            st32 = o.state().astype(np.float32).astype(np.float64)
+            o.set_state(st32)
+            ctx.set_state(0, st32[:, :3])
+            base = ctx.mass(0)
         fo = o.tag()
         fg = ctx.tag()
         assert np.array_equal(fo, fg), cycle
@@ -439,13 +446,10 @@ def test_tag_and_regrid_bit_exact(orc, prec):
             assert np.array_equal(g[:, 3], r[:, 3])
         nu, dts = o.advance(4, return_dt=True)
         ctx.step(len(dts), dts)
-        if prec == gf.GF_FP32:
-            # keep the two in lock step: the FP32 data decides the next flags
-            o.set_state(ctx.state(0))
     assert len(set(ctx.leaves(0)[:, 1])) >= 2
     M, cl, bd = ctx.mass(0)
     tol = 1e-12 if prec == gf.GF_FP64 else 1e-6
-    assert abs(M - m0 - cl - bd) <= tol * m0
+    assert abs((M - base[0]) - (cl - base[1]) - (bd - base[2])) <= tol * base[0]
 
 
 # ------------------------------------------------------------ invariants
