@@ -588,7 +588,12 @@ double orc_inflow_depth(double qbar, double hint, double mint, double g, double 
     return h;
 }
 
-/* Overwrite the ghost cells of the inflow segment after the wall rule. */
+/* Overwrite the ghost cells of the inflow segment after the wall rule
+ * (reading R32'): every ghost row along the side whose centre lies in the
+ * segment, the corner rows included, each from the tile cell next to it on
+ * the interior side (a ghost cell itself in the corner rows).  Two patches
+ * meeting inside the segment then hold the same ghost values where their
+ * tiles overlap, so the transverse fluxes at their shared face agree. */
 static void inflow_ghosts(orc_sim *s, leaf_t *L, double t)
 {
     int m = s->m, side = s->inflow_side, k, layer;
@@ -599,7 +604,7 @@ static void inflow_ghosts(orc_sim *s, leaf_t *L, double t)
     qtot = orc_hydrograph(s, t);
     qbar = qtot / width;
     if (qbar == 0.0) return; /* wall once the inflow has stopped */
-    for (k = 0; k < m; ++k) {
+    for (k = -2; k < m + 2; ++k) {
         int ic, jc, ig[2], jg[2], normal;
         double pos, sgn, h, hint, mint;
         if (side == 0 || side == 1) {

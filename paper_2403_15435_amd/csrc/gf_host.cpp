@@ -641,6 +641,7 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
         ScenDev &h = c->hs[(size_t)i];
         h.t = 0.0; h.dt = 0.0; h.t_end = d.t_end; h.manning_n = d.manning_n;
         h.inflow_lo = d.inflow_lo; h.inflow_hi = d.inflow_hi; h.inflow_side = d.inflow_side;
+        h.x0 = d.x0; h.y0 = d.y0;
         h.n_hydro = d.n_hydro;
         for (int k = 0; k < d.n_hydro; ++k) { h.hydro_t[k] = d.hydro[2 * k]; h.hydro_q[k] = d.hydro[2 * k + 1]; }
     }

@@ -50,6 +50,7 @@ struct ScenDev {
     double nu_last;
     double manning_n;
     double inflow_lo, inflow_hi;
+    double x0, y0;           // domain origin (cell centres x0 + (I + 1/2) dx)
     double hydro_t[16], hydro_q[16];
     int32_t n_hydro;
     int32_t inflow_side;

@@ -363,3 +363,22 @@ def test_roundoff_stays_bounded(oracle_mod):
     assert _perturbed_growth(oracle_mod, rough, 100) < 1e-10
     rough5 = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=5, radius=400.0, manning_n=0.05)
     assert _perturbed_growth(oracle_mod, rough5, 100) < 1e-10
+
+
+@pytest.mark.parametrize("lo,hi", [(900.0, 1100.0), (600.0, 800.0)])
+def test_inflow_volume_budget(oracle_mod, lo, hi):
+    """Volume change = volume through the open faces (inflow segment and the
+    extrapolation outflow) + clamp volume, to round-off, whether the inflow
+    segment straddles a patch boundary (900-1100 m crosses the boundary at
+    1000 m) or lies inside one patch side (600-800 m)."""
+    from helpers import init_oracle
+    sc = inputs.v_valley(level_max=1, m=16, mi=4, mj=2, lx=4000.0, ly=2000.0, dem_level=1, init_level=1)
+    sc.inflow_lo, sc.inflow_hi = lo, hi
+    o = oracle_mod.Oracle(sc)
+    init_oracle(o, sc)
+    o.set_time(4000.0)        # on the hydrograph's plateau
+    m0, cl0, bd0 = o.mass()
+    o.advance(20)
+    M, cl, bd = o.mass()
+    assert bd - bd0 != 0.0
+    assert abs((M - m0) - (cl - cl0) - (bd - bd0)) <= 1e-13 * m0
