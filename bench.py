@@ -6,9 +6,11 @@ cells as 64 x 64 patches of 32 x 32 on a 10 km square of seeded fractal
 terrain (100 +/- 50 m), circular reservoir of depth 20 m and radius 400 m,
 Manning n = 0.033, walls.  A step is two kernels: the classification and
 update of dry patches, then the full update of the others.  Reported beside
-it: the same run on the FP64 path, the step's HBM roofline fraction
-(algorithmic 28 B per FP32 cell update), the same grid fully wet, and the CPU
-oracle timed on a bounded sample of the same workload.
+it: the same run on the plain FP64 path (ghost fill into ghosted tiles in
+device memory, a step launch per level, the step length chosen on the host:
+the comparator of the speedup) and on the fused FP64 path, the step's HBM
+roofline fraction (algorithmic 28 B per FP32 cell update), the same grid fully
+wet, and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -38,13 +40,23 @@ def wet_workload():
     return inputs.wet_dambreak(level=6, m=32, L=10000.0, seed=2, radius=400.0, manning_n=0.033)
 
 
-def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False):
+def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False, plain=False):
     import torch
     import paper_2403_15435_amd as gf
     ctx = gf.Context([sc], precision=precision, max_patches=4096)
     ctx.set_initial(0)
-    ctx.step(warmup)
+    ctx.step(warmup, plain=plain)
     tuned = None
+    if plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.step(steps, plain=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out = {"wall": wall, "cell_updates": int(st.cell_updates), "steps": int(st.steps),
+               "rejected": int(st.rejected), "mass": ctx.mass(0).tolist()}
+        ctx.close()
+        return out
     if step_threads:
         ctx.set_step_threads(step_threads)
     else:
@@ -137,8 +149,10 @@ def main():
     ap.add_argument("--workload", choices=["reservoir", "wet"], default="reservoir",
                     help="run only this grid (counter collection); the JSON line is for the reservoir")
     ap.add_argument("--wet-steps", type=int, default=200, help="steps of the all-wet comparison run (0: skip)")
-    ap.add_argument("--precision", choices=["both", "f32", "f64"], default="both",
-                    help="run only one path (for counter collection); the JSON line needs both")
+    ap.add_argument("--precision", choices=["both", "f32", "f64", "plain"], default="both",
+                    help="run only one path (for counter collection; plain: the FP64 comparator); "
+                         "the JSON line needs all")
+    ap.add_argument("--plain-steps", type=int, default=0, help="steps of the plain FP64 run (0: the same as --steps)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -154,6 +168,12 @@ def main():
     nt = args.step_threads or None
     if args.fp64_steps <= 0:
         args.fp64_steps = args.steps
+    if args.plain_steps <= 0:
+        args.plain_steps = args.steps
+    if args.precision == "plain":
+        rp = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.plain_steps, plain=True)
+        print(f"[bench] plain fp64 done: {rp}", file=sys.stderr, flush=True)
+        return
     if args.precision == "f64":
         r64 = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.fp64_steps, nt)
         print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
@@ -164,6 +184,8 @@ def main():
         return
     r64 = run_gpu(sc, gf.GF_FP64, args.warmup, args.fp64_steps, nt)
     print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
+    rp = run_gpu(sc, gf.GF_FP64, args.warmup, args.plain_steps, plain=True)
+    print(f"[bench] plain fp64 done: {rp}", file=sys.stderr, flush=True)
     wet = None
     if args.wet_steps > 0:
         wsc = wet_workload()
@@ -180,6 +202,7 @@ def main():
                "step_threads": w32["step_threads"]}
     cups32 = r32["cell_updates"] / r32["wall"]
     cups64 = r64["cell_updates"] / r64["wall"]
+    cupsp = rp["cell_updates"] / rp["wall"]
     cells_per_launch = 4096 * 32 * 32
     avg_launch_s = r32["kernel_ms"] / max(r32["launches"], 1) / 1e3
     achieved = BYTES_PER_UPDATE["f32"] * cells_per_launch / avg_launch_s / 1e9
@@ -202,8 +225,12 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6,
                      "dry_kernel_us": 1e3 * r32["dry_kernel_ms"] / max(r32["launches"], 1),
                      "step_kernel_us": 1e3 * r32["step_kernel_ms"] / max(r32["launches"], 1)},
-        "fp64_plain": {"value": cups64, "unit": "cell-updates/s", "steps": r64["steps"],
-                       "speedup_fp32_over_fp64": cups32 / cups64},
+        "fp64_plain": {"value": cupsp, "unit": "cell-updates/s", "steps": rp["steps"],
+                       "path": "gf_step_plain: per step, ghost fill into ghosted tiles in HBM, one step launch per "
+                               "level from them, Courant number read back and dt chosen on the host",
+                       "speedup_fp32_fused_over_fp64_plain": cups32 / cupsp},
+        "fp64_fused": {"value": cups64, "unit": "cell-updates/s", "steps": r64["steps"],
+                       "speedup_fp32_over_fp64_fused": cups32 / cups64},
         "cpu_baseline": cpu,
         "wet_cell_fraction_end": r32.get("wet_cell_fraction"),
         "step_threads": r32.get("step_threads"),

@@ -142,6 +142,15 @@ int gf_get_ghosted(gf_ctx *ctx, int32_t scen, int64_t leaf, int32_t field, doubl
  * GF_E_CFL.  Ghost filling, the update, friction, positivity and refluxing
  * at coarse/fine faces all run inside.  `out` is nullable. */
 int gf_step(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
+/* The same steps by the plain path, the comparator for gf_step: per attempt,
+ * for every scenario and level one launch filling the ghosted tiles in device
+ * memory ((m+4)^2 cells x 4 fields per leaf), one launch updating each patch
+ * from its ghosted tile, then the largest Courant number of each scenario
+ * read back to the host, which accepts or rejects and chooses dt with the
+ * same arithmetic (Sections 3.2-3.3, eq. (wpa_update), eq. (manning)).
+ * Results equal gf_step's bit for bit; arguments, statistics and errors are
+ * as for gf_step.  The ghosted tiles stay readable with gf_get_ghosted. */
+int gf_step_plain(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
 
 /* Refinement flags of every leaf of every scenario, concatenated in scenario
  * then leaf order: +1 refine, -1 coarsen, 0 keep (the depth, free-surface

@@ -65,6 +65,10 @@ struct gf_ctx {
     unsigned *d_wet_count = nullptr;
     double prof_ms_dry = 0.0, prof_ms_step = 0.0;
     unsigned *d_queue = nullptr;
+    // plain path: work items grouped by (scenario, level), per-item Courant
+    // data, per-scenario ranges and results
+    int32_t *d_pitems = nullptr, *d_pnan = nullptr, *d_prange = nullptr;
+    double *d_pmax = nullptr, *d_pres = nullptr;
     bool flags_dirty = true;  // state changed from the host: recompute the dry flags
     size_t es = 8;
     hipStream_t stream = nullptr;
@@ -438,17 +442,45 @@ int refresh_dry_flags(gf_ctx *c)
     return GF_OK;
 }
 
+// Kernel arguments shared by the fused and the plain path.
+template <typename T>
+void fill_step_args(gf_ctx *c, StepArgs<T> &a, double dt_fixed, int mode, T tau)
+{
+    a.desc = c->d_desc; a.n_work = (int)c->desc.size(); a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
+    a.q0 = (T *)c->q[0]; a.q1 = (T *)c->q[1]; a.b = (const T *)c->b; a.bg = (const T *)c->bg;
+    a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
+    a.reg = (T *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
+    a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
+    a.tau = tau; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter;
+    a.queue = c->d_queue; a.persistent = 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
+    a.wet_list = c->d_wet; a.wet_count = c->d_wet_count;
+}
+
+int launch_reflux(gf_ctx *c)
+{
+    if (c->reflux.empty()) return GF_OK;
+    RefluxArgsBase r{};
+    r.tasks = c->d_reflux; r.n_tasks = (int)c->reflux.size(); r.scen = c->d_scen; r.cap = c->cap; r.tau64 = c->cfg.dry_tol;
+    hipError_t e;
+    if (c->prec == GF_FP32)
+        e = gf_launch_reflux_f32(r, (float *)c->q[0], (float *)c->q[1], (const float *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
+    else
+        e = gf_launch_reflux_f64(r, (double *)c->q[0], (double *)c->q[1], (const double *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "reflux launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
 int launch_step(gf_ctx *c, double dt_fixed, int mode)
 {
     const int n = (int)c->desc.size();
     hipError_t e;
-    if (mode != 2) {
+    {
         int rc = refresh_dry_flags(c);
         if (rc) return rc;
     }
     // workgroups: one per patch, or the resident count taking patches from the queue
     int grid = n;
-    if (c->sched_wg != 0 && mode != 2) {
+    if (c->sched_wg != 0) {
         int want = c->sched_wg;
         if (want < 0) {
             const int base = c->m == 16 ? 64 : 256;
@@ -472,30 +504,20 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         HIPCHK(c, hipEventRecord(c->ev[evk], c->stream));
     }
     // dry_kernel (classification and the dry update) then step_kernel on the
-    // wet list; a ghost fill (mode 2) runs step_kernel on every patch
-    auto fill = [&](auto &a, auto *q0, auto *q1, auto *b, auto *bg, auto *reg, auto *ghost, auto tau) {
-        a.desc = c->d_desc; a.n_work = n; a.scen = c->d_scen; a.n_scen = (int)c->sc.size();
-        a.q0 = q0; a.q1 = q1; a.b = b; a.bg = bg;
-        a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
-        a.reg = reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
-        a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
-        a.tau = tau; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter; a.ghost_out = ghost;
-        a.queue = c->d_queue; a.persistent = grid < n ? 1 : 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
-        a.wet_list = c->d_wet; a.wet_count = c->d_wet_count; a.all_items = mode == 2 ? 1 : 0;
-    };
+    // wet list
     if (c->prec == GF_FP32) {
         StepArgs<float> a{};
-        fill(a, (float *)c->q[0], (float *)c->q[1], (const float *)c->b, (const float *)c->bg, (float *)c->reg,
-             (float *)c->ghost, tau32(c->cfg.dry_tol));
-        e = mode == 2 ? hipSuccess : gf_launch_dry_f32(a, c->m, c->stream);
+        fill_step_args<float>(c, a, dt_fixed, mode, tau32(c->cfg.dry_tol));
+        a.persistent = grid < n ? 1 : 0;
+        e = gf_launch_dry_f32(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f32(a, c->m, c->step_threads, grid, c->stream);
     } else {
         StepArgs<double> a{};
-        fill(a, (double *)c->q[0], (double *)c->q[1], (const double *)c->b, (const double *)c->bg, (double *)c->reg,
-             (double *)c->ghost, c->cfg.dry_tol);
-        e = mode == 2 ? hipSuccess : gf_launch_dry_f64(a, c->m, c->stream);
+        fill_step_args<double>(c, a, dt_fixed, mode, c->cfg.dry_tol);
+        a.persistent = grid < n ? 1 : 0;
+        e = gf_launch_dry_f64(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f64(a, c->m, c->step_threads, grid, c->stream);
@@ -505,15 +527,142 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         HIPCHK(c, hipEventRecord(c->ev[evk + 2], c->stream));
         c->prof_launches++;
     }
-    if (mode == 0 && !c->reflux.empty()) {
-        RefluxArgsBase r{};
-        r.tasks = c->d_reflux; r.n_tasks = (int)c->reflux.size(); r.scen = c->d_scen; r.cap = c->cap; r.tau64 = c->cfg.dry_tol;
-        if (c->prec == GF_FP32)
-            e = gf_launch_reflux_f32(r, (float *)c->q[0], (float *)c->q[1], (const float *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
-        else
-            e = gf_launch_reflux_f64(r, (double *)c->q[0], (double *)c->q[1], (const double *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
-        if (e != hipSuccess) return fail(c, GF_E_HIP, "reflux launch: %s", hipGetErrorString(e));
+    if (mode == 0) return launch_reflux(c);
+    return GF_OK;
+}
+
+// The plain path's work list: patch indices grouped by (scenario, level), the
+// groups, and each scenario's range of the list.
+struct PlainGroup {
+    int32_t scen, begin, end;
+};
+
+int plain_setup(gf_ctx *c, std::vector<PlainGroup> &groups)
+{
+    const int n = (int)c->desc.size(), ns = (int)c->sc.size();
+    if (!c->ghost) {
+        const size_t TW = (size_t)c->m + 4;
+        HIPCHK(c, hipMalloc(&c->ghost, (size_t)c->cap * 4 * TW * TW * c->es));
     }
+    if (!c->d_pitems) {
+        HIPCHK(c, hipMalloc(&c->d_pitems, sizeof(int32_t) * (size_t)c->cap));
+        HIPCHK(c, hipMalloc(&c->d_pnan, sizeof(int32_t) * (size_t)c->cap));
+        HIPCHK(c, hipMalloc(&c->d_pmax, sizeof(double) * (size_t)c->cap));
+        HIPCHK(c, hipMalloc(&c->d_prange, sizeof(int32_t) * 2 * (size_t)ns));
+        HIPCHK(c, hipMalloc(&c->d_pres, sizeof(double) * 2 * (size_t)ns));
+    }
+    std::vector<int32_t> items((size_t)n);
+    for (int k = 0; k < n; ++k) items[(size_t)k] = k;
+    std::stable_sort(items.begin(), items.end(), [&](int32_t x, int32_t y) {
+        const PatchDesc &X = c->desc[(size_t)x], &Y = c->desc[(size_t)y];
+        return X.scen != Y.scen ? X.scen < Y.scen : X.level < Y.level;
+    });
+    groups.clear();
+    std::vector<int32_t> range(2 * (size_t)ns, 0);
+    for (int k = 0; k < n; ++k) {
+        const PatchDesc &P = c->desc[(size_t)items[(size_t)k]];
+        if (groups.empty() || groups.back().scen != P.scen || c->desc[(size_t)items[(size_t)groups.back().begin]].level != P.level)
+            groups.push_back({P.scen, k, k});
+        groups.back().end = k + 1;
+        if (range[2 * (size_t)P.scen + 1] == 0) range[2 * (size_t)P.scen] = k;
+        range[2 * (size_t)P.scen + 1] = k + 1;
+    }
+    if (n) HIPCHK(c, hipMemcpyAsync(c->d_pitems, items.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_prange, range.data(), sizeof(int32_t) * range.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int launch_ghost(gf_ctx *c, const int32_t *items, int n)
+{
+    hipError_t e;
+    if (c->prec == GF_FP32) {
+        StepArgs<float> a{};
+        fill_step_args<float>(c, a, -1.0, 0, tau32(c->cfg.dry_tol));
+        e = gf_launch_ghost_f32(a, items, n, (float *)c->ghost, c->m, c->stream);
+    } else {
+        StepArgs<double> a{};
+        fill_step_args<double>(c, a, -1.0, 0, c->cfg.dry_tol);
+        e = gf_launch_ghost_f64(a, items, n, (double *)c->ghost, c->m, c->stream);
+    }
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "ghost launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
+// One attempt of the plain path: for every active scenario, per level, the
+// ghost fill and then the step from the ghosted tiles; the Courant data
+// reduced per scenario and read back; the host accepts or rejects and
+// chooses the next step length with the same arithmetic as the device
+// controller of the fused path; then the reflux of accepted scenarios.
+int plain_attempt(gf_ctx *c, const std::vector<PlainGroup> &groups, double dt_fixed, int mode)
+{
+    const int ns = (int)c->sc.size();
+    const bool fixed = dt_fixed >= 0.0;
+    std::vector<char> act((size_t)ns);
+    for (int s = 0; s < ns; ++s) {
+        const ScenDev &D = c->hs[(size_t)s];
+        act[(size_t)s] = D.status == 0 && D.steps < D.target && D.t < D.t_end;
+    }
+    for (const PlainGroup &g : groups) {
+        if (!act[(size_t)g.scen]) continue;
+        int rc = launch_ghost(c, c->d_pitems + g.begin, g.end - g.begin);
+        if (rc) return rc;
+    }
+    hipError_t e = hipSuccess;
+    for (const PlainGroup &g : groups) {
+        if (!act[(size_t)g.scen]) continue;
+        const int n = g.end - g.begin;
+        if (c->prec == GF_FP32) {
+            StepArgs<float> a{};
+            fill_step_args<float>(c, a, dt_fixed, mode, tau32(c->cfg.dry_tol));
+            e = gf_launch_plain_f32(a, c->d_pitems + g.begin, n, (const float *)c->ghost, c->d_pmax + g.begin,
+                                    c->d_pnan + g.begin, c->m, c->stream);
+        } else {
+            StepArgs<double> a{};
+            fill_step_args<double>(c, a, dt_fixed, mode, c->cfg.dry_tol);
+            e = gf_launch_plain_f64(a, c->d_pitems + g.begin, n, (const double *)c->ghost, c->d_pmax + g.begin,
+                                    c->d_pnan + g.begin, c->m, c->stream);
+        }
+        if (e != hipSuccess) return fail(c, GF_E_HIP, "plain step launch: %s", hipGetErrorString(e));
+    }
+    e = c->prec == GF_FP32 ? gf_launch_cflred_f32(c->d_pmax, c->d_pnan, c->d_prange, ns, c->d_pres, c->stream)
+                           : gf_launch_cflred_f64(c->d_pmax, c->d_pnan, c->d_prange, ns, c->d_pres, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "Courant reduction launch: %s", hipGetErrorString(e));
+    std::vector<double> res(2 * (size_t)ns);
+    HIPCHK(c, hipMemcpyAsync(res.data(), c->d_pres, sizeof(double) * res.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool any_accepted = false;
+    for (int s = 0; s < ns; ++s) {
+        ScenDev &D = c->hs[(size_t)s];
+        D.accepted_last = 0;
+        if (!act[(size_t)s]) continue;
+        const double sm = res[2 * (size_t)s];
+        if (mode == 1) {
+            D.dt = sm > 0.0 ? c->cfg.cfl_desired / sm : 1.0;
+            continue;
+        }
+        double dtu = fixed ? dt_fixed : D.dt;
+        if (!fixed && D.t + dtu > D.t_end) dtu = D.t_end - D.t;
+        const double nu = dtu * sm;
+        D.dt_used = dtu;
+        D.nu_last = nu;
+        if (res[2 * (size_t)s + 1] != 0.0) { D.status = -6; continue; }
+        if (nu > c->cfg.cfl_max) {
+            if (fixed) { D.status = -5; continue; }
+            D.rejected += 1;
+            D.dt = dtu * c->cfg.cfl_desired / nu;
+            continue;
+        }
+        D.t = D.t + dtu;
+        D.steps += 1;
+        D.cur ^= 1;
+        D.accepted_last = 1;
+        any_accepted = true;
+        if (!fixed) D.dt = nu > 0.0 ? dtu * c->cfg.cfl_desired / nu : dtu;
+    }
+    int rc = push_scen(c);
+    if (rc) return rc;
+    if (mode == 0 && any_accepted) return launch_reflux(c);
     return GF_OK;
 }
 
@@ -694,7 +843,8 @@ void gf_destroy(gf_ctx *c)
     else (void)hipDeviceSynchronize();
     void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
-                  c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count};
+                  c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
+                  c->d_prange, c->d_pmax, c->d_pres};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -894,9 +1044,10 @@ int gf_fill_ghosts(gf_ctx *c)
         if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
     int rc = ensure_work(c);
     if (rc) return rc;
-    const size_t TW = (size_t)c->m + 4;
-    if (!c->ghost) HIPCHK(c, hipMalloc(&c->ghost, (size_t)c->cap * 4 * TW * TW * c->es));
-    rc = launch_step(c, -1.0, 2);
+    std::vector<PlainGroup> groups;
+    rc = plain_setup(c, groups);
+    if (rc) return rc;
+    rc = launch_ghost(c, c->d_pitems, (int)c->desc.size());
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return GF_OK;
@@ -918,6 +1069,30 @@ int gf_get_ghosted(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, double 
     else from_real<double>((const double *)tmp.data(), out, TW2);
     return GF_OK;
 }
+
+namespace {
+// statistics of a gf_step / gf_step_plain call and its status
+int step_result(gf_ctx *c, const std::vector<int64_t> &steps0, const std::vector<int64_t> &rej0, gf_step_stats *out)
+{
+    int status = GF_OK;
+    gf_step_stats st{};
+    st.t_min = 1e300; st.t_max = -1e300; st.dt_min = 1e300; st.dt_max = -1e300;
+    for (size_t i = 0; i < c->hs.size(); ++i) {
+        const ScenDev &h = c->hs[i];
+        if (h.status != 0 && status == GF_OK) status = h.status;
+        st.steps += h.steps - steps0[i];
+        st.rejected += h.rejected - rej0[i];
+        const int64_t cells = (int64_t)c->sc[i].leaves.size() * c->m * c->m;
+        st.cell_updates += (h.steps - steps0[i]) * cells;
+        st.t_min = std::min(st.t_min, h.t); st.t_max = std::max(st.t_max, h.t);
+        st.dt_min = std::min(st.dt_min, h.dt); st.dt_max = std::max(st.dt_max, h.dt);
+    }
+    if (out) *out = st;
+    if (status == -5) return fail(c, GF_E_CFL, "a fixed step exceeded the maximum Courant number");
+    if (status == -6) return fail(c, GF_E_NUMERIC, "non-finite state produced");
+    return status;
+}
+}  // namespace
 
 int gf_step(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *out)
 {
@@ -966,24 +1141,56 @@ int gf_step(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *ou
             if (rc) return rc;
         }
     }
-    int status = GF_OK;
-    gf_step_stats st{};
-    st.t_min = 1e300; st.t_max = -1e300; st.dt_min = 1e300; st.dt_max = -1e300;
+    return step_result(c, steps0, rej0, out);
+}
+
+int gf_step_plain(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *out)
+{
+    if (!c) return GF_E_INVALID;
+    if (nsteps < 0) return fail(c, GF_E_INVALID, "negative step count");
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    std::vector<PlainGroup> groups;
+    rc = plain_setup(c, groups);
+    if (rc) return rc;
+    std::vector<int64_t> steps0(c->hs.size()), rej0(c->hs.size());
     for (size_t i = 0; i < c->hs.size(); ++i) {
-        const ScenDev &h = c->hs[i];
-        if (h.status != 0 && status == GF_OK) status = h.status;
-        st.steps += h.steps - steps0[i];
-        st.rejected += h.rejected - rej0[i];
-        int64_t cells = 0;
-        for (size_t k = 0; k < c->sc[i].leaves.size(); ++k) cells += (int64_t)c->m * c->m;
-        st.cell_updates += (h.steps - steps0[i]) * cells;
-        st.t_min = std::min(st.t_min, h.t); st.t_max = std::max(st.t_max, h.t);
-        st.dt_min = std::min(st.dt_min, h.dt); st.dt_max = std::max(st.dt_max, h.dt);
+        ScenDev &h = c->hs[i];
+        h.status = 0;
+        h.target = h.steps + nsteps;
+        steps0[i] = h.steps;
+        rej0[i] = h.rejected;
     }
-    if (out) *out = st;
-    if (status == -5) return fail(c, GF_E_CFL, "a fixed step exceeded the maximum Courant number");
-    if (status == -6) return fail(c, GF_E_NUMERIC, "non-finite state produced");
-    return status;
+    rc = push_scen(c);
+    if (rc) return rc;
+    if (!dt_fixed) {
+        bool need = false;
+        for (auto &h : c->hs) need = need || h.dt <= 0.0;
+        if (need) {
+            rc = plain_attempt(c, groups, -1.0, 1);
+            if (rc) return rc;
+        }
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        rc = plain_attempt(c, groups, dt_fixed ? dt_fixed[k] : -1.0, 0);
+        if (rc) return rc;
+    }
+    if (!dt_fixed) {
+        // rejected attempts leave scenarios short of their target: keep going
+        for (int round = 0; round < 64; ++round) {
+            int64_t missing = 0;
+            for (auto &h : c->hs)
+                if (h.status == 0 && h.t < h.t_end) missing = std::max<int64_t>(missing, h.target - h.steps);
+            if (missing <= 0) break;
+            for (int64_t k = 0; k < missing; ++k) {
+                rc = plain_attempt(c, groups, -1.0, 0);
+                if (rc) return rc;
+            }
+        }
+    }
+    return step_result(c, steps0, rej0, out);
 }
 
 int gf_tag(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n)

@@ -86,8 +86,6 @@ struct StepArgs {
     uint8_t *dry0, *dry1;        // per slot and buffer: 1 iff every interior cell has h <= tau
     int32_t *wet_list;           // work items dry_kernel left for step_kernel
     unsigned int *wet_count;     // their number; reset to 0 by the last workgroup of step_kernel
-    int32_t all_items;           // 1: step_kernel takes every work item (ghost fill)
-    R *ghost_out;            // gf_fill_ghosts: [cap][4][(m+4)^2], else null
 };
 
 struct RefluxArgsBase {
@@ -120,7 +118,13 @@ struct RefluxArgsBase {
                                     const R *q0, const R *q1, int64_t cap, double *out, int m,     \
                                     hipStream_t s);                                                 \
     hipError_t gf_launch_transfer_##SFX(const void *tasks, int n, const gf::ScenDev *scen, R *q0, R *q1, \
-                                        const R *b, int64_t cap, double tau, int m, hipStream_t s);
+                                        const R *b, int64_t cap, double tau, int m, hipStream_t s);       \
+    hipError_t gf_launch_ghost_##SFX(const gf::StepArgs<R> &a, const int32_t *items, int n, R *ghost, int m, \
+                                     hipStream_t s);                                                  \
+    hipError_t gf_launch_plain_##SFX(const gf::StepArgs<R> &a, const int32_t *items, int n, const R *ghost, \
+                                     double *pmax, int32_t *pnan, int m, hipStream_t s);              \
+    hipError_t gf_launch_cflred_##SFX(const double *pmax, const int32_t *pnan, const int32_t *range, int n_scen, \
+                                      double *out, hipStream_t s);
 
 // regrid transfer task (layout shared with the kernels)
 namespace gf {

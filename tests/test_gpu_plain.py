@@ -1,0 +1,151 @@
+"""The plain path (gf_step_plain: ghost fill into ghosted tiles in device
+memory, a step launch per scenario and level, the step length chosen on the
+host) against the CPU oracle, bit for bit in FP64 with the oracle's own
+adaptive steps, and against the fused path (gf_step) in both precisions.
+Also the inflow boundary (Section 5.1.1) on both paths."""
+import numpy as np
+import pytest
+
+import paper_2403_15435_amd as gf
+from paper_2403_15435_amd import inputs
+from helpers import init_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _amr_leaves():
+    lv = [(0, 1, 0, 0), (0, 1, 1, 1)]
+    lv += [(0, 2, 2 + a, b) for b in range(2) for a in range(2)]
+    lv += [(0, 2, 0, 2), (0, 2, 1, 2), (0, 2, 1, 3)]
+    lv += [(0, 3, a, 6 + b) for b in range(2) for a in range(2)]
+    return np.array(lv, np.int32)
+
+
+def small_valley():
+    """The inflow valley on 4 x 2 trees of 16^2 patches at level 1 (31.25 m
+    cells, the 200 m inflow segment 6-7 cells wide), started on the
+    hydrograph's plateau (q = 5000 m^3/s)."""
+    sc = inputs.v_valley(level_max=1, m=16, mi=4, mj=2, lx=4000.0, ly=2000.0, dem_level=1, init_level=1)
+    sc.t_end = 1e9
+    return sc
+
+
+def _case(name):
+    if name == "reservoir":
+        sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
+        return [sc], None, 0.0, 60
+    if name == "amr":
+        sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+        sc.min_level, sc.max_level = 1, 3
+        return [sc], _amr_leaves(), 0.0, 40
+    if name == "valley":
+        return [small_valley()], None, 4000.0, 40
+    if name == "ensemble":
+        scs = inputs.ensemble_dambreaks(n_scen=3, master_seed=4100, sizes=(64, 128))
+        for sc in scs:
+            sc.t_end = 1e9
+        return scs, None, 0.0, 20
+    raise KeyError(name)
+
+
+def _oracles(orc, scs, leaves, t0):
+    out = []
+    for sc in scs:
+        o = orc.Oracle(sc, leaves=leaves) if leaves is not None else orc.Oracle(sc)
+        init_oracle(o, sc)
+        if t0:
+            o.set_time(t0)
+        out.append(o)
+    return out
+
+
+def _ctx(scs, leaves, prec, oracles=None, t0=0.0):
+    ctx = gf.Context(scs, precision=prec, max_patches=256)
+    for k in range(len(scs)):
+        if leaves is not None:
+            ctx.set_leaves(k, leaves)
+        if oracles is not None:
+            ctx.set_state(k, oracles[k].state())
+        else:
+            ctx.set_initial(k)
+        if t0:
+            ctx.set_time(k, t0)
+    return ctx
+
+
+@pytest.mark.parametrize("name", ["reservoir", "amr", "valley", "ensemble"])
+def test_plain_path_matches_oracle(orc, name):
+    """Adaptive steps chosen on the host: the same step lengths, times and
+    states as the oracle, bit for bit (refluxing on the AMR mesh, the inflow
+    ghost depth from eq. (riemann) / eq. (2-shock) on the valley)."""
+    scs, leaves, t0, n = _case(name)
+    os_ = _oracles(orc, scs, leaves, t0)
+    ctx = _ctx(scs, leaves, gf.GF_FP64, os_, t0)
+    m0 = [ctx.mass(k) for k in range(len(scs))]
+    print(f"plain {name}: {len(scs)} scenario(s), {sum(ctx.leaves(k).shape[0] for k in range(len(scs)))} leaves",
+          flush=True)
+    st = ctx.step(n, plain=True)
+    assert st.steps == n * len(scs)
+    for k, o in enumerate(os_):
+        o.advance(n)
+        t, dt, steps, rej = ctx.time(k)
+        assert (steps, rej) == (o.steps, o.rejected), (k, steps, o.steps, rej, o.rejected)
+        assert t == o.t and dt == o.dt, (k, t, o.t, dt, o.dt)
+        g, r = ctx.state(k), o.state()
+        same = np.array_equal(g[:, :3], r[:, :3])
+        print(f"  scenario {k}: t {t:.3f}, bit-identical {same}, max abs diff {np.abs(g[:, :3] - r[:, :3]).max():.3e}",
+              flush=True)
+        assert same
+        M, cl, bd = ctx.mass(k)
+        assert abs((M - m0[k][0]) - (cl - m0[k][1]) - (bd - m0[k][2])) <= 1e-12 * m0[k][0]
+        if name == "valley":
+            assert bd - m0[k][2] > 0.0     # water came in through the inflow segment
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP32, gf.GF_FP64])
+@pytest.mark.parametrize("name", ["reservoir", "amr", "valley"])
+def test_plain_path_equals_fused_path(name, prec):
+    """The two paths run the same arithmetic: identical states, times and
+    volume budgets after the same number of adaptive steps."""
+    scs, leaves, t0, n = _case(name)
+    a = _ctx(scs, leaves, prec, t0=t0)
+    b = _ctx(scs, leaves, prec, t0=t0)
+    a.step(n)
+    b.step(n, plain=True)
+    for k in range(len(scs)):
+        assert tuple(a.time(k)) == tuple(b.time(k))
+        assert np.array_equal(a.state(k), b.state(k))
+        assert np.array_equal(np.asarray(a.mass(k)), np.asarray(b.mass(k)))
+    # and the fused path continues from a state the plain path produced
+    a.step(5)
+    b.step(5)
+    for k in range(len(scs)):
+        assert np.array_equal(a.state(k), b.state(k))
+
+
+def test_fused_path_inflow_matches_oracle(orc):
+    """The inflow valley on the fused path, bit for bit with the oracle."""
+    scs, leaves, t0, n = _case("valley")
+    os_ = _oracles(orc, scs, leaves, t0)
+    ctx = _ctx(scs, leaves, gf.GF_FP64, os_, t0)
+    ctx.step(n)
+    os_[0].advance(n)
+    t, dt, steps, _ = ctx.time(0)
+    assert steps == os_[0].steps and t == os_[0].t and dt == os_[0].dt
+    assert np.array_equal(ctx.state(0)[:, :3], os_[0].state()[:, :3])
+
+
+def test_plain_fixed_step_above_cfl_is_refused():
+    scs, leaves, t0, n = _case("reservoir")
+    ctx = _ctx(scs, leaves, gf.GF_FP64)
+    with pytest.raises(gf.GFError) as e:
+        ctx.step(1, [50.0], plain=True)
+    assert e.value.code == gf.GF_E_CFL
+    assert ctx.time(0)[2] == 0
