@@ -54,6 +54,8 @@ def value_noise(x: np.ndarray, y: np.ndarray, seed: int, octaves: int = 5,
     """Fractal value noise at points (x, y); x, y broadcast together."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
+    if x.ndim == 2 and y.ndim == 2 and x.shape[0] == 1 and y.shape[1] == 1:
+        return _value_noise_grid(x[0], y[:, 0], seed, octaves, base_wavelength, lacunarity, persistence)
     x, y = np.broadcast_arrays(x, y)
     out = np.zeros(x.shape, dtype=np.float64)
     amp = 1.0
@@ -71,6 +73,41 @@ def value_noise(x: np.ndarray, y: np.ndarray, seed: int, octaves: int = 5,
         v10 = lattice_uniform(seed, o, ix + 1, iy)
         v01 = lattice_uniform(seed, o, ix, iy + 1)
         v11 = lattice_uniform(seed, o, ix + 1, iy + 1)
+        a = v00 + (v10 - v00) * tx
+        b = v01 + (v11 - v01) * tx
+        out += amp * (a + (b - a) * ty)
+        amp *= persistence
+        wl /= lacunarity
+    return out
+
+
+def _value_noise_grid(xr: np.ndarray, yc: np.ndarray, seed: int, octaves: int, base_wavelength: float,
+                      lacunarity: float, persistence: float) -> np.ndarray:
+    """value_noise on the grid (yc[j], xr[i]): the lattice values are drawn once
+    per lattice point and gathered; every grid value is formed by the same
+    operations as in value_noise, so the result is identical."""
+    out = np.zeros((yc.shape[0], xr.shape[0]), dtype=np.float64)
+    amp = 1.0
+    wl = base_wavelength
+    for o in range(octaves):
+        gx = xr / wl
+        gy = yc / wl
+        ix = np.floor(gx)
+        iy = np.floor(gy)
+        tx = _quintic(gx - ix)[None, :]
+        ty = _quintic(gy - iy)[:, None]
+        ix = ix.astype(np.int64)
+        iy = iy.astype(np.int64)
+        i0, j0 = int(ix.min()), int(iy.min())
+        li = np.arange(i0, int(ix.max()) + 2, dtype=np.int64)
+        lj = np.arange(j0, int(iy.max()) + 2, dtype=np.int64)
+        lat = lattice_uniform(seed, o, np.broadcast_to(li[None, :], (lj.shape[0], li.shape[0])),
+                              np.broadcast_to(lj[:, None], (lj.shape[0], li.shape[0])))
+        cx, cy = ix - i0, iy - j0
+        v00 = lat[np.ix_(cy, cx)]
+        v10 = lat[np.ix_(cy, cx + 1)]
+        v01 = lat[np.ix_(cy + 1, cx)]
+        v11 = lat[np.ix_(cy + 1, cx + 1)]
         a = v00 + (v10 - v00) * tx
         b = v01 + (v11 - v01) * tx
         out += amp * (a + (b - a) * ty)
