@@ -11,8 +11,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <unordered_map>
 #include <unordered_set>
+#include <new>
 #include <vector>
 
 using namespace gf;
@@ -32,12 +32,106 @@ inline uint64_t key_of(int level, int64_t PI, int64_t PJ)
     return ((uint64_t)(level + 1) << 56) | ((uint64_t)PI << 28) | (uint64_t)PJ;
 }
 
-inline uint64_t interleave(uint64_t x, uint64_t y)
+// Leaf key -> leaf index: open addressing with linear probing, capacity a
+// power of two kept at least twice the entries (keys never equal the empty
+// mark: their top byte is level + 1 <= 15).
+class LeafMap {
+    std::vector<uint64_t> keys_;
+    std::vector<int32_t> vals_;
+    size_t mask_ = 0, size_ = 0;
+    static constexpr uint64_t EMPTY = ~0ull;
+    void grow()
+    {
+        std::vector<uint64_t> k;
+        std::vector<int32_t> v;
+        k.swap(keys_);
+        v.swap(vals_);
+        reset(2 * size_ + 16);
+        for (size_t i = 0; i < k.size(); ++i)
+            if (k[i] != EMPTY) set(k[i], v[i]);
+    }
+    static uint64_t mix(uint64_t k)
+    {
+        k ^= k >> 33;
+        k *= 0xff51afd7ed558ccdull;
+        k ^= k >> 33;
+        return k;
+    }
+
+public:
+    void reset(size_t n)
+    {
+        size_t cap = 16;
+        while (cap < 2 * n + 2) cap <<= 1;
+        keys_.assign(cap, EMPTY);
+        vals_.assign(cap, -1);
+        mask_ = cap - 1;
+        size_ = 0;
+    }
+    void set(uint64_t k, int32_t v)
+    {
+        if (2 * (size_ + 1) > keys_.size()) grow();
+        size_t i = mix(k) & mask_;
+        while (keys_[i] != EMPTY && keys_[i] != k) i = (i + 1) & mask_;
+        if (keys_[i] == EMPTY) ++size_;
+        keys_[i] = k;
+        vals_[i] = v;
+    }
+    // insert k (value 1) if absent; true if it was absent
+    bool insert(uint64_t k)
+    {
+        if (get(k) >= 0) return false;
+        set(k, 1);
+        return true;
+    }
+    bool contains(uint64_t k) const { return get(k) >= 0; }
+    // -1 when absent
+    int32_t get(uint64_t k) const
+    {
+        if (keys_.empty()) return -1;
+        for (size_t i = mix(k) & mask_;; i = (i + 1) & mask_) {
+            if (keys_[i] == k) return vals_[i];
+            if (keys_[i] == EMPTY) return -1;
+        }
+    }
+};
+
+// Allocator of page-locked host memory: the patch descriptors are rebuilt
+// and uploaded after every regrid, and uploads from locked memory run at
+// full link speed without staging.
+template <typename T>
+struct PinnedAlloc {
+    using value_type = T;
+    PinnedAlloc() = default;
+    template <typename U>
+    PinnedAlloc(const PinnedAlloc<U> &) {}
+    T *allocate(size_t n)
+    {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, n * sizeof(T), hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
+        return (T *)p;
+    }
+    void deallocate(T *p, size_t) { (void)hipHostFree(p); }
+    template <typename U>
+    bool operator==(const PinnedAlloc<U> &) const { return true; }
+    template <typename U>
+    bool operator!=(const PinnedAlloc<U> &) const { return false; }
+};
+
+// bits of x (up to 32) spread to the even bit positions
+inline uint64_t spread_bits(uint64_t x)
 {
-    uint64_t k = 0;
-    for (int b = 0; b < 31; ++b) k |= ((x >> b) & 1ull) << (2 * b) | ((y >> b) & 1ull) << (2 * b + 1);
-    return k;
+    x &= 0xFFFFFFFFull;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
 }
+
+// Morton code: x in the even bits, y in the odd bits
+inline uint64_t interleave(uint64_t x, uint64_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
 
 struct Scen {
     gf_scenario_desc d{};
@@ -47,7 +141,7 @@ struct Scen {
     std::vector<double> dem;
     std::vector<std::vector<double>> pyr;   // levels 0..dem_level
     std::vector<Leaf> leaves;
-    std::unordered_map<uint64_t, int> map;  // key -> leaf index
+    LeafMap map;                            // key -> leaf index
     double clamp_base = 0.0, bnd_base = 0.0;
 };
 
@@ -69,6 +163,10 @@ struct gf_ctx {
     // data, per-scenario ranges and results
     int32_t *d_pitems = nullptr, *d_pnan = nullptr, *d_prange = nullptr;
     double *d_pmax = nullptr, *d_pres = nullptr;
+    // bathymetry of new leaves, staged for one upload and a scatter kernel
+    void *d_bstage = nullptr;
+    int32_t *d_bslots = nullptr;
+    int64_t bstage_cap = 0;   // leaves
     bool flags_dirty = true;  // state changed from the host: recompute the dry flags
     size_t es = 8;
     hipStream_t stream = nullptr;
@@ -91,7 +189,7 @@ struct gf_ctx {
     XferTaskH *d_xfer = nullptr;
     int64_t xfer_cap = 0;
     // host mirrors
-    std::vector<PatchDesc> desc;
+    std::vector<PatchDesc, PinnedAlloc<PatchDesc>> desc;
     std::vector<RefluxTask> reflux;
     std::vector<ScenDev> hs;
     std::vector<int8_t> last_flags;
@@ -239,39 +337,73 @@ void pack_bathy(const gf_ctx *c, const std::vector<double> &t, R *interior, R *r
         for (int j = 0; j < m; ++j) ring[r++] = (R)t[(size_t)((j + 2) * TW + (cols[cc] + 2))];
 }
 
+// Bathymetry (interior and halo ring) of the given leaves: packed on the host
+// leaf after leaf, one upload, then a kernel copies each to its slot.
 int upload_bathy(gf_ctx *c, const Scen &s, const std::vector<Leaf *> &leaves)
 {
     const int m = c->m, rs = ring_size(m);
-    const size_t MM = (size_t)m * m;
-    std::vector<double> tile;
-    std::vector<char> bi(c->es * MM), br(c->es * (size_t)rs);
-    for (Leaf *L : leaves) {
-        leaf_bathy_tile(c, s, *L, tile);
-        if (c->prec == GF_FP32) pack_bathy<float>(c, tile, (float *)bi.data(), (float *)br.data());
-        else pack_bathy<double>(c, tile, (double *)bi.data(), (double *)br.data());
-        HIPCHK(c, hipMemcpyAsync((char *)c->b + (size_t)L->slot * MM * c->es, bi.data(), bi.size(), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync((char *)c->bg + (size_t)L->slot * rs * c->es, br.data(), br.size(), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+    const size_t MM = (size_t)m * m, per = MM + (size_t)rs;
+    const int64_t n = (int64_t)leaves.size();
+    if (n == 0) return GF_OK;
+    if (n > c->bstage_cap) {
+        if (c->d_bstage) (void)hipFree(c->d_bstage);
+        if (c->d_bslots) (void)hipFree(c->d_bslots);
+        c->d_bstage = nullptr;
+        c->d_bslots = nullptr;
+        c->bstage_cap = 0;
+        const int64_t want = std::max<int64_t>(n, 256);
+        HIPCHK(c, hipMalloc(&c->d_bstage, (size_t)want * per * c->es));
+        HIPCHK(c, hipMalloc(&c->d_bslots, sizeof(int32_t) * (size_t)want));
+        c->bstage_cap = want;
     }
+    std::vector<char> host((size_t)n * per * c->es);
+    std::vector<int32_t> slots((size_t)n);
+    std::vector<double> tile;
+    for (int64_t j = 0; j < n; ++j) {
+        const Leaf &L = *leaves[(size_t)j];
+        slots[(size_t)j] = L.slot;
+        leaf_bathy_tile(c, s, L, tile);
+        char *dst = host.data() + (size_t)j * per * c->es;
+        if (c->prec == GF_FP32) pack_bathy<float>(c, tile, (float *)dst, (float *)dst + MM);
+        else pack_bathy<double>(c, tile, (double *)dst, (double *)dst + MM);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_bstage, host.data(), host.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_bslots, slots.data(), sizeof(int32_t) * slots.size(), hipMemcpyHostToDevice, c->stream));
+    const hipError_t e = c->prec == GF_FP32
+        ? gf_launch_bathy_f32((const float *)c->d_bstage, c->d_bslots, (int)n, (float *)c->b, (float *)c->bg, m, c->stream)
+        : gf_launch_bathy_f64((const double *)c->d_bstage, c->d_bslots, (int)n, (double *)c->b, (double *)c->bg, m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "bathymetry launch: %s", hipGetErrorString(e));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return GF_OK;
 }
 
 // ---------------------------------------------------------------- forest
+// Leaf order: tree (row-major), then Morton order of the leaf's corner at a
+// common resolution of 2^20 inside the tree.  A regrid emits children in
+// place of their parent in quadrant order (x low bit) and a parent in place of
+// its first child, which keeps this order; the sort only runs when the list
+// is out of order (leaves set from outside).
 void sort_leaves(const gf_ctx *c, Scen &s)
 {
     const int mi = s.d.mi;
-    std::sort(s.leaves.begin(), s.leaves.end(), [&](const Leaf &a, const Leaf &b) {
-        const int64_t ta = (a.PJ >> a.level) * mi + (a.PI >> a.level);
-        const int64_t tb = (b.PJ >> b.level) * mi + (b.PI >> b.level);
-        if (ta != tb) return ta < tb;
-        const uint64_t ka = interleave((uint64_t)(a.PI & ((1ll << a.level) - 1)) << (20 - a.level),
-                                       (uint64_t)(a.PJ & ((1ll << a.level) - 1)) << (20 - a.level));
-        const uint64_t kb = interleave((uint64_t)(b.PI & ((1ll << b.level) - 1)) << (20 - b.level),
-                                       (uint64_t)(b.PJ & ((1ll << b.level) - 1)) << (20 - b.level));
-        return ka < kb;
-    });
-    s.map.clear();
-    for (size_t k = 0; k < s.leaves.size(); ++k) s.map[key_of(s.leaves[k].level, s.leaves[k].PI, s.leaves[k].PJ)] = (int)k;
+    const size_t n = s.leaves.size();
+    std::vector<std::pair<int64_t, uint64_t>> key(n);
+    for (size_t k = 0; k < n; ++k) {
+        const Leaf &a = s.leaves[k];
+        key[k].first = (a.PJ >> a.level) * mi + (a.PI >> a.level);
+        key[k].second = interleave((uint64_t)(a.PI & ((1ll << a.level) - 1)) << (20 - a.level),
+                                   (uint64_t)(a.PJ & ((1ll << a.level) - 1)) << (20 - a.level));
+    }
+    if (!std::is_sorted(key.begin(), key.end())) {
+        std::vector<size_t> idx(n);
+        for (size_t k = 0; k < n; ++k) idx[k] = k;
+        std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
+        std::vector<Leaf> sorted(n);
+        for (size_t k = 0; k < n; ++k) sorted[k] = s.leaves[idx[k]];
+        s.leaves.swap(sorted);
+    }
+    s.map.reset(n);
+    for (size_t k = 0; k < n; ++k) s.map.set(key_of(s.leaves[k].level, s.leaves[k].PI, s.leaves[k].PJ), (int32_t)k);
     (void)c;
 }
 
@@ -279,14 +411,14 @@ void sort_leaves(const gf_ctx *c, Scen &s)
 int cover(const gf_ctx *c, const Scen &s, int l, int64_t I, int64_t J, int &rel)
 {
     const int m = c->m;
-    auto it = s.map.find(key_of(l, I / m, J / m));
-    if (it != s.map.end()) { rel = 0; return it->second; }
+    int k = s.map.get(key_of(l, I / m, J / m));
+    if (k >= 0) { rel = 0; return k; }
     if (l > 0) {
-        it = s.map.find(key_of(l - 1, (I >> 1) / m, (J >> 1) / m));
-        if (it != s.map.end()) { rel = -1; return it->second; }
+        k = s.map.get(key_of(l - 1, (I >> 1) / m, (J >> 1) / m));
+        if (k >= 0) { rel = -1; return k; }
     }
-    it = s.map.find(key_of(l + 1, (2 * I) / m, (2 * J) / m));
-    if (it != s.map.end()) { rel = 1; return it->second; }
+    k = s.map.get(key_of(l + 1, (2 * I) / m, (2 * J) / m));
+    if (k >= 0) { rel = 1; return k; }
     return -1;
 }
 
@@ -844,7 +976,7 @@ void gf_destroy(gf_ctx *c)
     void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
-                  c->d_prange, c->d_pmax, c->d_pres};
+                  c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -1226,7 +1358,7 @@ namespace {
 struct Topo {
     const gf_ctx *c;
     const Scen *s;
-    std::unordered_set<uint64_t> internal;   // keys of nodes that have children
+    LeafMap internal;                         // keys of nodes that have children
     bool inside(int l, int64_t X, int64_t Y) const
     {
         return X >= 0 && Y >= 0 && X < ((int64_t)s->d.mi << l) && Y < ((int64_t)s->d.mj << l);
@@ -1235,7 +1367,7 @@ struct Topo {
     {
         for (int a = l - 1; a >= 0; --a) {
             const uint64_t k = key_of(a, X >> (l - a), Y >> (l - a));
-            if (!internal.insert(k).second) break;
+            if (!internal.insert(k)) break;
         }
     }
     // any leaf finer than level l+1 touching the level-l patch (X, Y)?  That is
@@ -1248,7 +1380,7 @@ struct Topo {
         for (auto &o : off) {
             const int64_t xx = x0 + o[0], yy = y0 + o[1];
             if (!inside(l + 1, xx, yy)) continue;
-            if (internal.count(key_of(l + 1, xx, yy))) return true;
+            if (internal.contains(key_of(l + 1, xx, yy))) return true;
         }
         return false;
     }
@@ -1277,25 +1409,40 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
         off += n;
         std::vector<char> ref((size_t)n, 0), coa((size_t)n, 0);
         for (int64_t k = 0; k < n; ++k) ref[(size_t)k] = fl[k] > 0 && s.leaves[(size_t)k].level < s.d.max_level;
-        // 2:1 face+corner balance closure of the refinement
+        // 2:1 face+corner balance closure of the refinement: a leaf must
+        // refine when one of the twelve next-finer cells around it has
+        // children.  The mesh was balanced before, so only a leaf one level
+        // coarser than, and next to, a node that gains children can break
+        // the rule; the closure follows a worklist of such nodes.
         Topo T{c, &s, {}};
+        T.internal.reset((size_t)n);
+        struct Node { int l; int64_t X, Y; };
+        std::vector<Node> work;
         for (int64_t k = 0; k < n; ++k) {
             const Leaf &L = s.leaves[(size_t)k];
-            if (ref[(size_t)k]) { T.internal.insert(key_of(L.level, L.PI, L.PJ)); }
+            if (ref[(size_t)k]) {
+                T.internal.insert(key_of(L.level, L.PI, L.PJ));
+                work.push_back({L.level, L.PI, L.PJ});
+            }
             T.add_ancestors(L.level, L.PI, L.PJ);
         }
-        for (bool changed = true; changed;) {
-            changed = false;
-            for (int64_t k = 0; k < n; ++k) {
-                const Leaf &L = s.leaves[(size_t)k];
-                if (ref[(size_t)k]) continue;
-                if (T.finer_than_next(L.level, L.PI, L.PJ)) {
+        while (!work.empty()) {
+            const Node N = work.back();
+            work.pop_back();
+            if (N.l == 0) continue;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (!dx && !dy) continue;
+                    const int64_t xx = N.X + dx, yy = N.Y + dy;
+                    if (!T.inside(N.l, xx, yy)) continue;
+                    const int kk = s.map.get(key_of(N.l - 1, xx >> 1, yy >> 1));
+                    if (kk < 0 || ref[(size_t)kk]) continue;
+                    const Leaf &L = s.leaves[(size_t)kk];
                     if (L.level >= s.d.max_level) return fail(c, GF_E_INVALID, "balance needs a level beyond max_level");
-                    ref[(size_t)k] = 1;
+                    ref[(size_t)kk] = 1;
                     T.internal.insert(key_of(L.level, L.PI, L.PJ));
-                    changed = true;
+                    work.push_back({L.level, L.PI, L.PJ});
                 }
-            }
         }
         // coarsening of complete families whose parent stays balanced
         for (int64_t k = 0; k < n; ++k) {
@@ -1304,9 +1451,8 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
             int sib[4];
             bool ok = true;
             for (int q = 0; q < 4 && ok; ++q) {
-                auto it = s.map.find(key_of(L.level, L.PI + (q & 1), L.PJ + (q >> 1)));
-                if (it == s.map.end()) { ok = false; break; }
-                sib[q] = it->second;
+                sib[q] = s.map.get(key_of(L.level, L.PI + (q & 1), L.PJ + (q >> 1)));
+                if (sib[q] < 0) { ok = false; break; }
                 if (fl[sib[q]] >= 0 || ref[(size_t)sib[q]]) ok = false;
             }
             if (!ok) continue;
@@ -1344,8 +1490,8 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
                 pend.push_back({2, k, 0});
             }
         }
-        std::vector<Leaf> old = s.leaves;
-        auto oldmap = s.map;
+        const std::vector<Leaf> &old = s.leaves;
+        const auto &oldmap = s.map;
         // transfer tasks (read the old slots, write the fresh ones)
         for (size_t j = 0; j < nl.size(); ++j) {
             const Pending &p = pend[j];
@@ -1359,13 +1505,13 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
             } else {
                 t.kind = 1;
                 const Leaf &L = old[(size_t)p.src];
-                for (int q = 0; q < 4; ++q) t.src[q] = old[(size_t)oldmap[key_of(L.level, L.PI + (q & 1), L.PJ + (q >> 1))]].slot;
+                for (int q = 0; q < 4; ++q) t.src[q] = old[(size_t)oldmap.get(key_of(L.level, L.PI + (q & 1), L.PJ + (q >> 1)))].slot;
             }
             xfer.push_back(t);
         }
         rc = upload_bathy(c, s, fresh);
         if (rc) return rc;
-        s.leaves = nl;
+        s.leaves = std::move(nl);
         sort_leaves(c, s);
         total += (int64_t)s.leaves.size();
     }

@@ -452,6 +452,34 @@ def test_tag_and_regrid_bit_exact(orc, prec):
     assert abs((M - base[0]) - (cl - base[1]) - (bd - base[2])) <= tol * base[0]
 
 
+@pytest.mark.parametrize("seed", [11, 12])
+def test_random_flag_regrids_bit_exact(orc, seed):
+    """Seeded random refine/coarsen flags over many cycles (deep balance
+    cascades, families coarsened back): the same leaves, bathymetry and moved
+    state as the oracle, bit for bit, and the volume kept."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=4, radius=600.0, dem_level=3)
+    sc.min_level, sc.max_level = 0, 5
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=2048)
+    ctx.set_state(0, o.state()[:, :3])
+    rng = np.random.default_rng(seed)
+    m0 = ctx.mass(0)[0]
+    for cycle in range(8):
+        lv = o.leaves()
+        # mostly refine early, mostly coarsen late; limits respected by both
+        p = [0.3, 0.45, 0.25] if cycle < 4 else [0.9, 0.08, 0.02]
+        fl = rng.choice(np.array([-1, 0, 1], np.int8), size=lv.shape[0], p=p)
+        no = o.regrid(fl)
+        ng = ctx.regrid(fl)
+        assert no == ng, cycle
+        assert np.array_equal(o.leaves(), ctx.leaves(0)), cycle
+        g, r = ctx.state(0), o.state()
+        assert np.array_equal(g, r), cycle
+    assert len(set(ctx.leaves(0)[:, 1].tolist())) >= 3
+    assert abs(ctx.mass(0)[0] - m0) <= 1e-12 * m0
+
+
 # ------------------------------------------------------------ invariants
 @pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
 def test_lake_at_rest_bit_exact(orc, prec):
