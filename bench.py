@@ -70,17 +70,140 @@ def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False,
     wall = time.perf_counter() - t0
     launches, ms = ctx.profile_read()
     ms_dry, ms_step = ctx.profile_split()
+    full, stable = ctx.profile_patches()
     ctx.profile_enable(False)
     cells = int(st.cell_updates)
     mass = ctx.mass(0)
     out = {"wall": wall, "cell_updates": cells, "steps": int(st.steps), "launches": launches,
            "kernel_ms": ms, "dry_kernel_ms": ms_dry, "step_kernel_ms": ms_step,
-           "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads(), "tuned": tuned}
+           "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads(), "tuned": tuned,
+           "full_patch_updates": full, "stable_dry_patches": stable}
     if wet_fraction:
         h = ctx.state(0)[:, 0]
         out["wet_cell_fraction"] = float(np.count_nonzero(h > 1e-4)) / h.size
     ctx.close()
     return out
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def valley_amr(steps, warmup, regrid_every=4, t0=4000.0):
+    """The AMR workload: the inflow valley (20 km x 10 km, 16 x 8 trees, levels
+    0-6 of 32 x 32 patches, finest cells 0.61 m), refined from level 0 around
+    its normal-depth flood by the plain tagger, started on the hydrograph's
+    plateau (5000 m^3/s); tag and regrid every `regrid_every` steps.  Run on
+    the fused FP32 path, the fused FP64 path and the plain FP64 path from the
+    same mesh and state (the FP32 one, widened)."""
+    import paper_2403_15435_amd as gf
+    from paper_2403_15435_amd import inputs
+    sc = inputs.v_valley()
+    cap = 48000
+    base = gf.Context([sc], precision=gf.GF_FP32, max_patches=cap)
+    base.set_initial(0)
+    for _ in range(sc.max_level - sc.min_level):
+        base.tag()
+        base.regrid(None)
+        base.set_initial(0)
+    leaves0, state0 = base.leaves(0), base.state(0)
+    base.close()
+    print(f"[bench] valley mesh: {leaves0.shape[0]} leaves, levels {sorted(set(leaves0[:, 1].tolist()))}",
+          file=sys.stderr, flush=True)
+    out = {"workload": "AMR inflow valley: 20 km x 10 km V valley (side slope 0.05, 2 m rms fractal roughness), "
+                       "16x8 trees, levels 0-6 of 32x32 patches (finest 0.61 m), inflow 5000 m^3/s over 200 m, "
+                       "n = 0.04, extrapolation outflow, walls; plain tagger and regrid every 4 steps",
+           "leaves_start": int(leaves0.shape[0]), "steps": steps, "regrid_every": regrid_every}
+    for name, prec, plain in (("fp32_fused", gf.GF_FP32, False), ("fp64_fused", gf.GF_FP64, False),
+                              ("fp64_plain", gf.GF_FP64, True)):
+        ctx = gf.Context([sc], precision=prec, max_patches=cap)
+        ctx.set_leaves(0, leaves0)
+        ctx.set_state(0, state0[:, :3])
+        ctx.set_time(0, t0)
+        if not plain:
+            ctx.autotune(steps=3)
+
+        def cycle():
+            _sync()
+            a = time.perf_counter()
+            st = ctx.step(regrid_every, plain=plain)
+            _sync()
+            b = time.perf_counter()
+            ctx.tag()
+            ctx.regrid(None)
+            return st, b - a, time.perf_counter() - b
+        for _ in range(max(warmup // regrid_every, 1)):
+            cycle()
+        m0 = ctx.mass(0)
+        t_step = t_regrid = 0.0
+        cells = 0
+        for _ in range(steps // regrid_every):
+            st, ts, tr = cycle()
+            t_step += ts
+            t_regrid += tr
+            cells += int(st.cell_updates)
+        M = ctx.mass(0)
+        cups = cells / t_step
+        out[name] = {"step_cell_updates_per_s": cups, "end_to_end_cell_updates_per_s": cells / (t_step + t_regrid),
+                     "step_s": t_step, "tag_regrid_s": t_regrid, "leaves_end": int(ctx.leaves(0).shape[0]),
+                     "budget_residual_rel": float(((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) / M[0])}
+        if prec == gf.GF_FP32:
+            out[name]["hbm_frac_algorithmic"] = cups * BYTES_PER_UPDATE["f32"] / (HBM_PEAK_GBS * 1e9)
+        print(f"[bench] valley {name}: {out[name]}", file=sys.stderr, flush=True)
+        ctx.close()
+    out["speedup_fp32_fused_over_fp64_plain"] = (out["fp32_fused"]["step_cell_updates_per_s"]
+                                                 / out["fp64_plain"]["step_cell_updates_per_s"])
+    return out
+
+
+def ensemble(steps, warmup, n_scen=256):
+    """The batched workload: 256 independent dam breaks on seeded fractal
+    terrain (grids of 64^2 to 512^2 cells as 32 x 32 patches, n ~ U[0.02,
+    0.06], breach widths U[50, 500] m), every scenario with its own adaptive
+    step, all in one launch per step on the fused path (one launch per
+    scenario on the plain path); the same initial state (FP32, widened) on
+    every path."""
+    import paper_2403_15435_amd as gf
+    from paper_2403_15435_amd import inputs
+    scs = inputs.ensemble_dambreaks(n_scen=n_scen)
+    cap = sum(int(round((s.x1 - s.x0) / 10.0)) ** 2 // (32 * 32) for s in scs) + 64
+    base = gf.Context(scs, precision=gf.GF_FP32, max_patches=cap)
+    states = [base.set_initial(k) for k in range(len(scs))]
+    base.close()
+    out = {"workload": f"ensemble of {n_scen} dam breaks, grids in {{64,128,256,512}}^2 (dx 10 m) as 32x32 patches, "
+                       "seeded fractal terrain, n ~ U[0.02,0.06], breach U[50,500] m, walls",
+           "patches": cap - 64, "steps_per_scenario": steps}
+    for name, prec, plain in (("fp32_fused", gf.GF_FP32, False), ("fp64_fused", gf.GF_FP64, False),
+                              ("fp64_plain", gf.GF_FP64, True)):
+        ctx = gf.Context(scs, precision=prec, max_patches=cap)
+        for k, st0 in enumerate(states):
+            ctx.set_state(k, st0[:, :3])
+        if not plain:
+            ctx.autotune(steps=3)
+        ctx.step(warmup, plain=plain)
+        _sync()
+        a = time.perf_counter()
+        st = ctx.step(steps, plain=plain)
+        _sync()
+        wall = time.perf_counter() - a
+        cups = int(st.cell_updates) / wall
+        out[name] = {"cell_updates_per_s": cups, "s": wall, "rejected": int(st.rejected)}
+        if prec == gf.GF_FP32:
+            out[name]["hbm_frac_algorithmic"] = cups * BYTES_PER_UPDATE["f32"] / (HBM_PEAK_GBS * 1e9)
+        print(f"[bench] ensemble {name}: {out[name]}", file=sys.stderr, flush=True)
+        ctx.close()
+    out["speedup_fp32_fused_over_fp64_plain"] = out["fp32_fused"]["cell_updates_per_s"] / out["fp64_plain"]["cell_updates_per_s"]
+    return out
+
+
+def guarded(fn, *a):
+    """An extra workload's section, or the error that stopped it."""
+    try:
+        return fn(*a)
+    except Exception as e:  # reported in the JSON line, which still prints
+        print(f"[bench] {fn.__name__} failed: {e!r}", file=sys.stderr, flush=True)
+        return {"error": repr(e)}
 
 
 def cpu_baseline(sc, steps=48):
@@ -153,6 +276,10 @@ def main():
                     help="run only one path (for counter collection; plain: the FP64 comparator); "
                          "the JSON line needs all")
     ap.add_argument("--plain-steps", type=int, default=0, help="steps of the plain FP64 run (0: the same as --steps)")
+    ap.add_argument("--amr-steps", type=int, default=400, help="steps of each AMR valley run (0: skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=200, help="steps of each ensemble run (0: skip)")
+    ap.add_argument("--only", choices=["valley", "ensemble"], default=None,
+                    help="run only this extra workload and print its section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -162,6 +289,12 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
+    if args.only == "valley":
+        print(json.dumps(valley_amr(args.amr_steps, 40)))
+        return
+    if args.only == "ensemble":
+        print(json.dumps(ensemble(args.ensemble_steps, 10)))
+        return
     import paper_2403_15435_amd as gf
     sc = workload() if args.workload == "reservoir" else wet_workload()
     print(f"[bench] workload ready: {sc.name}, {4096} patches", file=sys.stderr, flush=True)
@@ -206,6 +339,8 @@ def main():
     cells_per_launch = 4096 * 32 * 32
     avg_launch_s = r32["kernel_ms"] / max(r32["launches"], 1) / 1e3
     achieved = BYTES_PER_UPDATE["f32"] * cells_per_launch / avg_launch_s / 1e9
+    amr = guarded(valley_amr, args.amr_steps, 40) if args.amr_steps > 0 else None
+    ens = guarded(ensemble, args.ensemble_steps, 10) if args.ensemble_steps > 0 else None
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sc)
@@ -224,7 +359,13 @@ def main():
                      "kernel": f"one step = dry_kernel<32> + step_kernel<32,{r32['step_threads']}> (fp32)",
                      "avg_launch_us": avg_launch_s * 1e6,
                      "dry_kernel_us": 1e3 * r32["dry_kernel_ms"] / max(r32["launches"], 1),
-                     "step_kernel_us": 1e3 * r32["step_kernel_ms"] / max(r32["launches"], 1)},
+                     "step_kernel_us": 1e3 * r32["step_kernel_ms"] / max(r32["launches"], 1),
+                     "patches_full_update_per_step": r32["full_patch_updates"] / max(r32["launches"], 1),
+                     "patches_stable_dry_per_step": r32["stable_dry_patches"] / max(r32["launches"], 1),
+                     "step_kernel_hbm_frac": (BYTES_PER_UPDATE["f32"] * 1024 * r32["full_patch_updates"]
+                                              / max(r32["launches"], 1)
+                                              / (1e-3 * r32["step_kernel_ms"] / max(r32["launches"], 1))
+                                              / 1e9 / HBM_PEAK_GBS)},
         "fp64_plain": {"value": cupsp, "unit": "cell-updates/s", "steps": rp["steps"],
                        "path": "gf_step_plain: per step, ghost fill into ghosted tiles in HBM, one step launch per "
                                "level from them, Courant number read back and dt chosen on the host",
@@ -235,6 +376,8 @@ def main():
         "wet_cell_fraction_end": r32.get("wet_cell_fraction"),
         "step_threads": r32.get("step_threads"),
         "all_wet": wet,
+        "amr_valley": amr,
+        "ensemble": ens,
     }
     print(json.dumps(line))
 

@@ -208,6 +208,11 @@ int gf_set_schedule(gf_ctx *ctx, int32_t workgroups);
 int gf_profile_enable(gf_ctx *ctx, int32_t on);
 int gf_profile_read(gf_ctx *ctx, int64_t *launches, double *ms_total);
 int gf_profile_split(gf_ctx *ctx, double *ms_dry, double *ms_step);
+/* Patch counts over the profiled steps (since gf_profile_enable(ctx, 1)):
+ * patches that went through the full update, and dry patches found stable
+ * (both state buffers already holding the dry update's result, so that
+ * nothing is read or written for them).  Synchronises the stream. */
+int gf_profile_patches(gf_ctx *ctx, int64_t *full_updates, int64_t *stable_dry);
 
 /* ------------------------------------------------------------------------
  * Learned refinement tagger (for callers that regrid less often than they

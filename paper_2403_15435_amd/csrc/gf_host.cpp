@@ -155,6 +155,8 @@ struct gf_ctx {
     int sched_wg = -1;        // step workgroups: 0 one per patch, > 0 that many persistent, -1 the resident count
     int resident[3] = {0, 0, 0}; // resident workgroup count per step-thread choice (cached)
     uint8_t *dry[2] = {nullptr, nullptr};   // per slot and buffer: all interior cells dry
+    uint8_t *d_dstab = nullptr;              // per slot: dry-update state (unknown / last read buffer / stable)
+    unsigned long long *d_stats = nullptr;   // patches through the step kernel, stable dry patches
     int32_t *d_wet = nullptr;                // wet work items of the current step
     unsigned *d_wet_count = nullptr;
     double prof_ms_dry = 0.0, prof_ms_step = 0.0;
@@ -565,10 +567,10 @@ int refresh_dry_flags(gf_ctx *c)
     hipError_t e;
     if (c->prec == GF_FP32)
         e = gf_launch_dryflag_f32(c->d_desc, n, c->d_scen, (const float *)c->q[0], (const float *)c->q[1], c->dry[0],
-                                  c->dry[1], c->cap, tau32(c->cfg.dry_tol), c->m, c->stream);
+                                  c->dry[1], c->d_dstab, c->cap, tau32(c->cfg.dry_tol), c->m, c->stream);
     else
         e = gf_launch_dryflag_f64(c->d_desc, n, c->d_scen, (const double *)c->q[0], (const double *)c->q[1], c->dry[0],
-                                  c->dry[1], c->cap, c->cfg.dry_tol, c->m, c->stream);
+                                  c->dry[1], c->d_dstab, c->cap, c->cfg.dry_tol, c->m, c->stream);
     if (e != hipSuccess) return fail(c, GF_E_HIP, "dry-flag launch: %s", hipGetErrorString(e));
     c->flags_dirty = false;
     return GF_OK;
@@ -586,6 +588,7 @@ void fill_step_args(gf_ctx *c, StepArgs<T> &a, double dt_fixed, int mode, T tau)
     a.tau = tau; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter;
     a.queue = c->d_queue; a.persistent = 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
     a.wet_list = c->d_wet; a.wet_count = c->d_wet_count;
+    a.dstab = c->d_dstab; a.stats = c->prof ? c->d_stats : nullptr;
 }
 
 int launch_reflux(gf_ctx *c)
@@ -593,6 +596,7 @@ int launch_reflux(gf_ctx *c)
     if (c->reflux.empty()) return GF_OK;
     RefluxArgsBase r{};
     r.tasks = c->d_reflux; r.n_tasks = (int)c->reflux.size(); r.scen = c->d_scen; r.cap = c->cap; r.tau64 = c->cfg.dry_tol;
+    r.dstab = c->d_dstab;
     hipError_t e;
     if (c->prec == GF_FP32)
         e = gf_launch_reflux_f32(r, (float *)c->q[0], (float *)c->q[1], (const float *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
@@ -947,6 +951,7 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     ok = ok && alloc((void **)&c->d_queue, 64) && alloc((void **)&c->dry[0], (size_t)c->cap) &&
          alloc((void **)&c->dry[1], (size_t)c->cap);
     ok = ok && alloc((void **)&c->d_wet, sizeof(int32_t) * (size_t)c->cap) && alloc((void **)&c->d_wet_count, 64);
+    ok = ok && alloc((void **)&c->d_dstab, (size_t)c->cap) && alloc((void **)&c->d_stats, 64);
     ok = ok && alloc((void **)&c->d_thr, sizeof(double) * 2 * c->sc.size()) && alloc((void **)&c->d_lev, sizeof(int32_t) * 2 * c->sc.size());
     if (!ok) {
         gf_destroy(c);
@@ -976,7 +981,7 @@ void gf_destroy(gf_ctx *c)
     void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
-                  c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots};
+                  c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -2105,6 +2110,9 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
         }
     c->prof = prof0;
     c->prof_launches = 0;
+    // the trials may have rewritten face records of patches the snapshot
+    // holds as stable: every patch goes back to full dry updates
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_dstab, 0, (size_t)c->cap, c->stream);
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(snap);
     if (e != hipSuccess) return fail(c, GF_E_HIP, "autotune snapshot: %s", hipGetErrorString(e));
@@ -2126,10 +2134,25 @@ int gf_profile_split(gf_ctx *c, double *ms_dry, double *ms_step)
     return GF_OK;
 }
 
+int gf_profile_patches(gf_ctx *c, int64_t *full_updates, int64_t *stable_dry)
+{
+    if (!c) return GF_E_INVALID;
+    unsigned long long v[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(v, c->d_stats, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (full_updates) *full_updates = (int64_t)v[0];
+    if (stable_dry) *stable_dry = (int64_t)v[1];
+    return GF_OK;
+}
+
 int gf_profile_enable(gf_ctx *c, int32_t on)
 {
     if (!c) return GF_E_INVALID;
-    if (on && !c->prof) { c->prof_launches = 0; c->prof_ms = 0.0; }
+    if (on && !c->prof) {
+        c->prof_launches = 0;
+        c->prof_ms = 0.0;
+        HIPCHK(c, hipMemsetAsync(c->d_stats, 0, 2 * sizeof(unsigned long long), c->stream));
+    }
     c->prof = on != 0;
     return GF_OK;
 }

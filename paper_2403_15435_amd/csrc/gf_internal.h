@@ -86,6 +86,11 @@ struct StepArgs {
     uint8_t *dry0, *dry1;        // per slot and buffer: 1 iff every interior cell has h <= tau
     int32_t *wet_list;           // work items dry_kernel left for step_kernel
     unsigned int *wet_count;     // their number; reset to 0 by the last workgroup of step_kernel
+    // per slot: 0 unknown; 1 + 2c: the last update was a full dry update
+    // reading buffer c; 4 stable: both buffers hold the same dry state, a
+    // fixed point of the dry update (which then writes nothing)
+    uint8_t *dstab;
+    unsigned long long *stats;   // [0] patches through step_kernel, [1] stable dry patches (or null)
 };
 
 struct RefluxArgsBase {
@@ -94,6 +99,7 @@ struct RefluxArgsBase {
     ScenDev *scen;
     int64_t cap;
     double tau64;
+    uint8_t *dstab;          // per-slot dry-update state, cleared for corrected patches
 };
 
 }  // namespace gf
@@ -106,7 +112,7 @@ struct RefluxArgsBase {
     int gf_step_resident_##SFX(int m, int nt);                                                     \
     hipError_t gf_launch_dryflag_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,     \
                                        const R *q0, const R *q1, uint8_t *f0, uint8_t *f1,         \
-                                       int64_t cap, R tau, int m, hipStream_t s);                  \
+                                       uint8_t *dstab, int64_t cap, R tau, int m, hipStream_t s);  \
     hipError_t gf_launch_reflux_##SFX(const gf::RefluxArgsBase &a, R *q0, R *q1, const R *reg,     \
                                       double *ca0, double *ca1, uint8_t *f0, uint8_t *f1, int m,   \
                                       hipStream_t s);                                               \

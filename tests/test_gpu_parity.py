@@ -272,6 +272,55 @@ def test_autotune_leaves_state_unchanged(tmp_path):
     assert ctxs[0].time(0) == ctxs[1].time(0)
 
 
+def test_autotune_on_amr_mesh_keeps_bits(tmp_path):
+    """On a mesh with coarse/fine faces (face records feed the refluxing),
+    steps after the tuner's trials give the same bits as without tuning."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+    sc.min_level, sc.max_level = 1, 3
+    ctxs = []
+    for tune in (False, True):
+        ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+        ctx.set_leaves(0, amr_mesh_16())
+        ctx.set_initial(0)
+        ctx.step(6)
+        if tune:
+            ctx.autotune(steps=3, cache=str(tmp_path / "tune_amr.txt"))
+        ctx.step(30)
+        ctxs.append(ctx)
+    assert ctxs[0].time(0) == ctxs[1].time(0)
+    assert np.array_equal(ctxs[0].state(0), ctxs[1].state(0))
+    assert np.array_equal(ctxs[0].mass(0), ctxs[1].mass(0))
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_stable_dry_patches_are_skipped_exactly(orc, prec):
+    """Dry patches found stable (both buffers hold the dry update's result)
+    are neither read nor written; the run still equals the oracle (FP64 bit
+    for bit; FP32 against the fused step's own first run)."""
+    sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
+    ctx = gf.Context([sc], precision=prec, max_patches=64)
+    ctx.set_initial(0)
+    ctx.profile_enable(True)
+    ctx.step(60)
+    full, stable = ctx.profile_patches()
+    ctx.profile_enable(False)
+    print(f"60 steps x 64 patches: {full} full updates, {stable} stable dry patches skipped", flush=True)
+    assert stable > 0 and full > 0
+    if prec == gf.GF_FP64:
+        o = orc.Oracle(sc)
+        init_oracle(o, sc)
+        o.advance(60)
+        assert ctx.time(0)[0] == o.t
+        assert np.array_equal(ctx.state(0)[:, :3], o.state()[:, :3])
+    else:
+        # the plain path never skips: the same bits
+        ref = gf.Context([sc], precision=prec, max_patches=64)
+        ref.set_initial(0)
+        ref.step(60, plain=True)
+        assert np.array_equal(ctx.state(0), ref.state(0))
+        assert np.array_equal(ctx.mass(0), ref.mass(0))
+
+
 def test_adaptive_step_controller(orc):
     """Library-chosen step lengths follow the same controller: first step from
     the speed pass, then dt cfl/nu, truncated at t_end."""
