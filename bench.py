@@ -197,6 +197,106 @@ def ensemble(steps, warmup, n_scen=256):
     return out
 
 
+def _finest_depth(sc, leaves, st, level):
+    """Depth of an AMR state projected (piecewise constant) onto one uniform level."""
+    m = sc.m
+    out = np.zeros((sc.mj * m << level, sc.mi * m << level))
+    for k, (t, l, ix, iy) in enumerate(np.asarray(leaves)):
+        r = 1 << (level - l)
+        PI = (t % sc.mi) * (1 << l) + ix
+        PJ = (t // sc.mi) * (1 << l) + iy
+        out[PJ * m * r:(PJ + 1) * m * r, PI * m * r:(PI + 1) * m * r] = np.kron(st[k, 0], np.ones((r, r)))
+    return out
+
+
+def learned_tagger(n_train=50, n_eval=10, steps=2000, window=16, check=4, iters=400, batch=256):
+    """The learned tagger on the reservoir geometry as AMR: 10 km square,
+    levels 0-6 of 32 x 32 patches (finest 4.88 m), reservoir r = 400 m with
+    its centre drawn from U[2.5 km, 7.5 km]^2 by the seed.  Trained on the GPU
+    from plain-tagger windows (a sample every 16 steps: every refine label,
+    twice as many others drawn at random) of seeds 5001.., evaluated on the
+    unseen seeds 5051..: the plain tagger every 4 steps (the judge), every 16
+    steps, and the network every 16 steps with the plain-tagger fallback at
+    the 4-step checks."""
+    import paper_2403_15435_amd as gf
+    from paper_2403_15435_amd import inputs
+    cap = 12000
+
+    def make(seed):
+        sc = inputs.adaptive_reservoir(seed, L=10000.0, m=32, max_level=6, dem_level=6, radius=400.0)
+        ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=cap)
+        ctx.set_initial(0)
+        for _ in range(sc.max_level):
+            ctx.tag()
+            ctx.regrid(None)
+            ctx.set_initial(0)
+        return sc, ctx
+    rng = np.random.default_rng(0)
+    X, Y = [], []
+    t0 = time.perf_counter()
+    for j in range(n_train):
+        sc, ctx = make(5001 + j)
+        for _ in range(steps // window):
+            F, y = ctx.net_collect(window, check)
+            keep = np.flatnonzero(y == 2)
+            rest = np.flatnonzero(y != 2)
+            take = min(rest.size, 2 * keep.size + 8)
+            keep = np.concatenate([keep, rng.choice(rest, size=take, replace=False)]) if take else keep
+            X.append(F[keep].astype(np.float32))
+            Y.append(y[keep])
+        ctx.close()
+        print(f"[bench] learned: collected seed {5001 + j}: {sum(a.shape[0] for a in X)} samples, "
+              f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    counts = np.bincount(Y, minlength=3)
+    cw = counts.sum() / (3.0 * np.maximum(counts, 1))
+    sc, ctx = make(5001)
+    ctx.net_set_params(inputs.cnn_init_params(0))
+    losses = []
+    t1 = time.perf_counter()
+    for _ in range(iters):
+        idx = rng.choice(Y.size, size=min(batch, Y.size), replace=False)
+        losses.append(ctx.net_train_step(X[idx].astype(np.float64), Y[idx], cw, lr=3e-3))
+    _sync()
+    t_train = time.perf_counter() - t1
+    params = ctx.net_params()
+    ctx.close()
+    print(f"[bench] learned: trained on {Y.size} samples {counts.tolist()}, loss {np.mean(losses[:10]):.3f} -> "
+          f"{np.mean(losses[-10:]):.3f}", file=sys.stderr, flush=True)
+    names = {gf.GF_RUN_PLAIN: "plain_every_4", gf.GF_RUN_SPARSE: "plain_every_16", gf.GF_RUN_LEARNED: "learned_every_16"}
+    acc = {v: {"regrids": 0, "forced_regrids": 0, "checks": 0, "misses": 0, "leaf_steps": 0, "seconds": 0.0,
+               "max_abs_dh_vs_plain": [], "budget_residual_rel": []} for v in names.values()}
+    for j in range(n_eval):
+        hp = None
+        for mode in (gf.GF_RUN_PLAIN, gf.GF_RUN_SPARSE, gf.GF_RUN_LEARNED):
+            sc, c2 = make(5051 + j)
+            c2.net_set_params(params)
+            m0 = c2.mass(0)
+            st = c2.run(steps, mode, check, window)
+            M = c2.mass(0)
+            h = _finest_depth(sc, c2.leaves(0), c2.state(0), sc.max_level)
+            hp = h if mode == gf.GF_RUN_PLAIN else hp
+            a = acc[names[mode]]
+            for k in ("regrids", "forced_regrids", "checks", "misses", "leaf_steps"):
+                a[k] += int(getattr(st, k))
+            a["seconds"] += st.seconds
+            a["max_abs_dh_vs_plain"].append(float(np.abs(h - hp).max()))
+            a["budget_residual_rel"].append(float(abs((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) / m0[0]))
+            c2.close()
+        print(f"[bench] learned: evaluated seed {5051 + j}", file=sys.stderr, flush=True)
+    for a in acc.values():
+        a["miss_rate"] = a["misses"] / max(a["checks"], 1)
+        d = a.pop("max_abs_dh_vs_plain")
+        a["max_abs_dh_vs_plain_m"] = {"max": max(d), "median": float(np.median(d))}
+        a["budget_residual_rel_max"] = max(a.pop("budget_residual_rel"))
+    return {"workload": "reservoir geometry as AMR: 10 km fractal terrain, levels 0-6 of 32x32 patches, reservoir "
+                        "h=20 m r=400 m at a seeded centre, n=0.033; FP32",
+            "train_seeds": n_train, "eval_seeds": n_eval, "steps_per_run": steps, "samples": int(Y.size),
+            "classes_coarsen_keep_refine": counts.tolist(), "train_iters": iters, "batch": batch,
+            "train_s": t_train, "loss_start_end": [float(np.mean(losses[:10])), float(np.mean(losses[-10:]))],
+            "modes": acc}
+
+
 def guarded(fn, *a):
     """An extra workload's section, or the error that stopped it."""
     try:
@@ -278,7 +378,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=0, help="steps of the plain FP64 run (0: the same as --steps)")
     ap.add_argument("--amr-steps", type=int, default=400, help="steps of each AMR valley run (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=200, help="steps of each ensemble run (0: skip)")
-    ap.add_argument("--only", choices=["valley", "ensemble"], default=None,
+    ap.add_argument("--only", choices=["valley", "ensemble", "learned"], default=None,
                     help="run only this extra workload and print its section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM byte counters)")
@@ -294,6 +394,9 @@ def main():
         return
     if args.only == "ensemble":
         print(json.dumps(ensemble(args.ensemble_steps, 10)))
+        return
+    if args.only == "learned":
+        print(json.dumps(learned_tagger()))
         return
     import paper_2403_15435_amd as gf
     sc = workload() if args.workload == "reservoir" else wet_workload()

@@ -20,7 +20,7 @@ UNITS = [
     ("gf_kernels_f32.hip", ["-ffp-contract=fast"]),
     ("gf_kernels_f64.hip", ["-ffp-contract=off"]),
     ("gf_net.hip", ["-ffp-contract=off"]),
-    ("gf_host.cpp", ["-ffp-contract=off"]),
+    ("gf_host.cpp", ["-ffp-contract=off", "-pthread"]),
 ]
 
 
@@ -58,7 +58,7 @@ def build(verbose: bool = False) -> str:
             print(out)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     return LIB
 

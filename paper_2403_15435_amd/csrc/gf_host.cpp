@@ -13,6 +13,7 @@
 #include <string>
 #include <unordered_set>
 #include <new>
+#include <thread>
 #include <vector>
 
 using namespace gf;
@@ -169,6 +170,11 @@ struct gf_ctx {
     void *d_bstage = nullptr;
     int32_t *d_bslots = nullptr;
     int64_t bstage_cap = 0;   // leaves
+    // state transfers: packed staging (bytes) and the slot list
+    void *d_sstage = nullptr;
+    size_t sstage_bytes = 0;
+    int32_t *d_sslots = nullptr;
+    int64_t sslots_cap = 0;
     bool flags_dirty = true;  // state changed from the host: recompute the dry flags
     size_t es = 8;
     hipStream_t stream = nullptr;
@@ -339,6 +345,45 @@ void pack_bathy(const gf_ctx *c, const std::vector<double> &t, R *interior, R *r
         for (int j = 0; j < m; ++j) ring[r++] = (R)t[(size_t)((j + 2) * TW + (cols[cc] + 2))];
 }
 
+// element access helpers for the state buffers
+inline size_t fstride(const gf_ctx *c) { return (size_t)c->cap * c->m * c->m; }
+
+// Device staging for state transfers of a scenario's leaves: `bytes` of
+// staging and the leaves' slots uploaded in leaf order.
+int stage_slots(gf_ctx *c, const Scen &s, size_t bytes)
+{
+    const int64_t n = (int64_t)s.leaves.size();
+    if (bytes > c->sstage_bytes) {
+        if (c->d_sstage) (void)hipFree(c->d_sstage);
+        c->d_sstage = nullptr;
+        c->sstage_bytes = 0;
+        HIPCHK(c, hipMalloc(&c->d_sstage, bytes));
+        c->sstage_bytes = bytes;
+    }
+    if (n > c->sslots_cap) {
+        if (c->d_sslots) (void)hipFree(c->d_sslots);
+        c->d_sslots = nullptr;
+        c->sslots_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_sslots, sizeof(int32_t) * (size_t)std::max<int64_t>(n, 256)));
+        c->sslots_cap = std::max<int64_t>(n, 256);
+    }
+    std::vector<int32_t> slots((size_t)n);
+    for (int64_t k = 0; k < n; ++k) slots[(size_t)k] = s.leaves[(size_t)k].slot;
+    if (n) HIPCHK(c, hipMemcpyAsync(c->d_sslots, slots.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int launch_state(gf_ctx *c, int kind, const void *a, const void *b, int n, void *out)
+{
+    const int64_t fs = (int64_t)fstride(c);
+    const hipError_t e = c->prec == GF_FP32
+        ? gf_launch_state_f32(kind, (const float *)a, (const float *)b, c->d_sslots, n, fs, (float *)out, c->m, c->stream)
+        : gf_launch_state_f64(kind, (const double *)a, (const double *)b, c->d_sslots, n, fs, (double *)out, c->m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "state transfer launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
 // Bathymetry (interior and halo ring) of the given leaves: packed on the host
 // leaf after leaf, one upload, then a kernel copies each to its slot.
 int upload_bathy(gf_ctx *c, const Scen &s, const std::vector<Leaf *> &leaves)
@@ -434,79 +479,129 @@ int32_t take_slot(gf_ctx *c)
 
 void give_slot(gf_ctx *c, int32_t s) { c->free_slots.push_back(s); }
 
-// work list: PatchDesc per leaf (scenario order, leaf order) and reflux tasks
-int rebuild_work(gf_ctx *c)
+// Descriptor of one leaf (halo sources, coarse/fine roles) and, when it is
+// the coarse side of a coarse/fine face, its reflux task.  Reads the forest
+// only.  Returns false with a message on an unbalanced or uncovered mesh.
+bool leaf_desc(const gf_ctx *c, int si, const Scen &s, const Leaf &L, PatchDesc &P, RefluxTask &T, bool &has_task,
+               char *err, size_t errn)
 {
     const int m = c->m;
-    c->desc.clear();
-    c->reflux.clear();
-    static const int reg_i0[12] = {-2, -2, 0, 0, 0, 0, 0, 0, -2, 0, -2, 0};
-    for (int si = 0; si < (int)c->sc.size(); ++si) {
-        Scen &s = c->sc[(size_t)si];
-        for (const Leaf &L : s.leaves) {
-            PatchDesc P{};
-            P.slot = L.slot; P.scen = si; P.level = L.level;
-            P.PI = (int32_t)L.PI; P.PJ = (int32_t)L.PJ;
-            const int64_t ni = NI(c, s, L.level), nj = NJ(c, s, L.level);
-            P.dx = DXl(c, s, L.level); P.dy = DYl(c, s, L.level);
-            P.xlo = s.d.x0 + (double)(L.PI * m) * P.dx;
-            P.ylo = s.d.y0 + (double)(L.PJ * m) * P.dy;
-            P.phys = (L.PI == 0 ? 1 : 0) | ((L.PI + 1) * m == ni ? 2 : 0) | (L.PJ == 0 ? 4 : 0) | ((L.PJ + 1) * m == nj ? 8 : 0);
-            for (int f = 0; f < 4; ++f) { P.bc[f] = s.d.bc[f]; P.cf_face[f] = -1; P.cf_role[f] = 0; }
-            (void)reg_i0;
-            for (int r = 0; r < 12; ++r) {
-                int i0, j0;
-                switch (r) {
-                case 0: i0 = -2; j0 = 0; break;
-                case 1: i0 = -2; j0 = m / 2; break;
-                case 2: i0 = m; j0 = 0; break;
-                case 3: i0 = m; j0 = m / 2; break;
-                case 4: i0 = 0; j0 = -2; break;
-                case 5: i0 = m / 2; j0 = -2; break;
-                case 6: i0 = 0; j0 = m; break;
-                case 7: i0 = m / 2; j0 = m; break;
-                case 8: i0 = -2; j0 = -2; break;
-                case 9: i0 = m; j0 = -2; break;
-                case 10: i0 = -2; j0 = m; break;
-                default: i0 = m; j0 = m; break;
-                }
-                const int64_t I = L.PI * m + i0, J = L.PJ * m + j0;
-                HaloSrc &h = P.src[r];
-                if (I < 0 || I >= ni || J < 0 || J >= nj) { h.kind = HK_PHYS; h.slot = -1; h.oi = h.oj = 0; continue; }
-                int rel;
-                const int k = cover(c, s, L.level, I, J, rel);
-                if (k < 0) return fail(c, GF_E_INVALID, "scenario %d: leaf (l%d,%lld,%lld) has an unbalanced or uncovered neighbour",
-                                       si, L.level, (long long)L.PI, (long long)L.PJ);
-                const Leaf &S = s.leaves[(size_t)k];
-                h.slot = S.slot;
-                if (rel == 0) { h.kind = HK_SAME; h.oi = (int32_t)((L.PI - S.PI) * m); h.oj = (int32_t)((L.PJ - S.PJ) * m); }
-                else if (rel == -1) { h.kind = HK_COARSE; h.oi = (int32_t)(L.PI * m - 2 * S.PI * m); h.oj = (int32_t)(L.PJ * m - 2 * S.PJ * m); }
-                else { h.kind = HK_FINE; h.oi = (int32_t)(2 * L.PI * m - S.PI * m); h.oj = (int32_t)(2 * L.PJ * m - S.PJ * m); }
-            }
-            for (int f = 0; f < 4; ++f) {
-                const HaloSrc &a = P.src[2 * f], &b2 = P.src[2 * f + 1];
-                if (a.kind == HK_FINE && b2.kind == HK_FINE) { P.cf_role[f] = 1; P.cf_face[f] = L.slot * 4 + f; }
-                else if (a.kind == HK_COARSE) { P.cf_role[f] = 2; P.cf_face[f] = L.slot * 4 + f; }
-                else if ((a.kind == HK_FINE) != (b2.kind == HK_FINE))
-                    return fail(c, GF_E_INVALID, "scenario %d: mixed-level face", si);
-            }
-            {
-                RefluxTask T{};
-                bool any = false;
-                T.slot = L.slot; T.scen = si; T.area = P.dx * P.dy;
-                for (int f = 0; f < 4; ++f) {
-                    T.reg_c[f] = -1;
-                    if (P.cf_role[f] != 1) continue;
-                    any = true;
-                    T.reg_c[f] = L.slot * 4 + f;
-                    T.reg_f[f][0] = P.src[2 * f].slot * 4 + (f ^ 1);
-                    T.reg_f[f][1] = P.src[2 * f + 1].slot * 4 + (f ^ 1);
-                }
-                if (any) c->reflux.push_back(T);
-            }
-            c->desc.push_back(P);
+    P = PatchDesc{};
+    P.slot = L.slot; P.scen = si; P.level = L.level;
+    P.PI = (int32_t)L.PI; P.PJ = (int32_t)L.PJ;
+    const int64_t ni = NI(c, s, L.level), nj = NJ(c, s, L.level);
+    P.dx = DXl(c, s, L.level); P.dy = DYl(c, s, L.level);
+    P.xlo = s.d.x0 + (double)(L.PI * m) * P.dx;
+    P.ylo = s.d.y0 + (double)(L.PJ * m) * P.dy;
+    P.phys = (L.PI == 0 ? 1 : 0) | ((L.PI + 1) * m == ni ? 2 : 0) | (L.PJ == 0 ? 4 : 0) | ((L.PJ + 1) * m == nj ? 8 : 0);
+    for (int f = 0; f < 4; ++f) { P.bc[f] = s.d.bc[f]; P.cf_face[f] = -1; P.cf_role[f] = 0; }
+    for (int r = 0; r < 12; ++r) {
+        int i0, j0;
+        switch (r) {
+        case 0: i0 = -2; j0 = 0; break;
+        case 1: i0 = -2; j0 = m / 2; break;
+        case 2: i0 = m; j0 = 0; break;
+        case 3: i0 = m; j0 = m / 2; break;
+        case 4: i0 = 0; j0 = -2; break;
+        case 5: i0 = m / 2; j0 = -2; break;
+        case 6: i0 = 0; j0 = m; break;
+        case 7: i0 = m / 2; j0 = m; break;
+        case 8: i0 = -2; j0 = -2; break;
+        case 9: i0 = m; j0 = -2; break;
+        case 10: i0 = -2; j0 = m; break;
+        default: i0 = m; j0 = m; break;
+        }
+        const int64_t I = L.PI * m + i0, J = L.PJ * m + j0;
+        HaloSrc &h = P.src[r];
+        if (I < 0 || I >= ni || J < 0 || J >= nj) { h.kind = HK_PHYS; h.slot = -1; h.oi = h.oj = 0; continue; }
+        int rel;
+        const int k = cover(c, s, L.level, I, J, rel);
+        if (k < 0) {
+            snprintf(err, errn, "scenario %d: leaf (l%d,%lld,%lld) has an unbalanced or uncovered neighbour", si, L.level,
+                     (long long)L.PI, (long long)L.PJ);
+            return false;
+        }
+        const Leaf &S = s.leaves[(size_t)k];
+        h.slot = S.slot;
+        if (rel == 0) { h.kind = HK_SAME; h.oi = (int32_t)((L.PI - S.PI) * m); h.oj = (int32_t)((L.PJ - S.PJ) * m); }
+        else if (rel == -1) { h.kind = HK_COARSE; h.oi = (int32_t)(L.PI * m - 2 * S.PI * m); h.oj = (int32_t)(L.PJ * m - 2 * S.PJ * m); }
+        else { h.kind = HK_FINE; h.oi = (int32_t)(2 * L.PI * m - S.PI * m); h.oj = (int32_t)(2 * L.PJ * m - S.PJ * m); }
+    }
+    for (int f = 0; f < 4; ++f) {
+        const HaloSrc &a = P.src[2 * f], &b2 = P.src[2 * f + 1];
+        if (a.kind == HK_FINE && b2.kind == HK_FINE) { P.cf_role[f] = 1; P.cf_face[f] = L.slot * 4 + f; }
+        else if (a.kind == HK_COARSE) { P.cf_role[f] = 2; P.cf_face[f] = L.slot * 4 + f; }
+        else if ((a.kind == HK_FINE) != (b2.kind == HK_FINE)) {
+            snprintf(err, errn, "scenario %d: mixed-level face", si);
+            return false;
         }
     }
+    T = RefluxTask{};
+    has_task = false;
+    T.slot = L.slot; T.scen = si; T.area = P.dx * P.dy;
+    for (int f = 0; f < 4; ++f) {
+        T.reg_c[f] = -1;
+        if (P.cf_role[f] != 1) continue;
+        has_task = true;
+        T.reg_c[f] = L.slot * 4 + f;
+        T.reg_f[f][0] = P.src[2 * f].slot * 4 + (f ^ 1);
+        T.reg_f[f][1] = P.src[2 * f + 1].slot * 4 + (f ^ 1);
+    }
+    return true;
+}
+
+// work list: PatchDesc per leaf (scenario order, leaf order) and reflux tasks
+// in the same order.  Large meshes are described by several host threads,
+// each on a contiguous range of leaves.
+int rebuild_work(gf_ctx *c)
+{
+    std::vector<std::pair<int, int64_t>> first;   // (scenario, global index of its first leaf)
+    int64_t total = 0;
+    for (int si = 0; si < (int)c->sc.size(); ++si) {
+        first.push_back({si, total});
+        total += (int64_t)c->sc[(size_t)si].leaves.size();
+    }
+    c->desc.resize((size_t)total);
+    std::vector<RefluxTask> task((size_t)total);
+    std::vector<char> has((size_t)total, 0);
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nth = (int)std::min<int64_t>(std::min<unsigned>(hw, 16u), std::max<int64_t>(1, total / 2048));
+    std::vector<std::string> errs((size_t)nth);
+    std::vector<int64_t> err_at((size_t)nth, -1);
+    auto work = [&](int t) {
+        const int64_t lo = total * t / nth, hi = total * (t + 1) / nth;
+        size_t sp = 0;
+        while (sp + 1 < first.size() && first[sp + 1].second <= lo) ++sp;
+        char buf[256];
+        for (int64_t g = lo; g < hi; ++g) {
+            while (sp + 1 < first.size() && first[sp + 1].second <= g) ++sp;
+            const int si = first[sp].first;
+            const Scen &s = c->sc[(size_t)si];
+            bool ht = false;
+            if (!leaf_desc(c, si, s, s.leaves[(size_t)(g - first[sp].second)], c->desc[(size_t)g], task[(size_t)g], ht, buf,
+                           sizeof buf)) {
+                errs[(size_t)t] = buf;
+                err_at[(size_t)t] = g;
+                return;
+            }
+            has[(size_t)g] = ht;
+        }
+    };
+    if (nth == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t) pool.emplace_back(work, t);
+        for (auto &th : pool) th.join();
+    }
+    for (int t = 0; t < nth; ++t)
+        if (err_at[(size_t)t] >= 0) {
+            c->desc.clear();
+            return fail(c, GF_E_INVALID, "%s", errs[(size_t)t].c_str());
+        }
+    c->reflux.clear();
+    for (int64_t g = 0; g < total; ++g)
+        if (has[(size_t)g]) c->reflux.push_back(task[(size_t)g]);
     if ((int64_t)c->desc.size() > c->desc_cap) {
         if (c->d_desc) (void)hipFree(c->d_desc);
         if (c->d_flags) (void)hipFree(c->d_flags);
@@ -550,8 +645,6 @@ int ensure_work(gf_ctx *c)
     return GF_OK;
 }
 
-// element access helpers for the state buffers
-inline size_t fstride(const gf_ctx *c) { return (size_t)c->cap * c->m * c->m; }
 
 float tau32(double tau)
 {
@@ -981,7 +1074,8 @@ void gf_destroy(gf_ctx *c)
     void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
-                  c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats};
+                  c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats,
+                  c->d_sstage, c->d_sslots};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -1049,11 +1143,10 @@ int gf_set_leaves(gf_ctx *c, int32_t scen, const int32_t *tlxy, int64_t n)
     for (Leaf &L : s.leaves) L.slot = take_slot(c);
     sort_leaves(c, s);
     // zero the state of the new slots in both buffers
-    const size_t MM = (size_t)c->m * c->m;
-    for (const Leaf &L : s.leaves)
-        for (int bf = 0; bf < 2; ++bf)
-            for (int f = 0; f < 3; ++f)
-                HIPCHK(c, hipMemsetAsync((char *)c->q[bf] + ((size_t)f * fstride(c) + (size_t)L.slot * MM) * c->es, 0, MM * c->es, c->stream));
+    rc = stage_slots(c, s, 0);
+    if (rc) return rc;
+    rc = launch_state(c, 2, nullptr, c->q[1], (int)s.leaves.size(), c->q[0]);
+    if (rc) return rc;
     std::vector<Leaf *> all;
     for (auto &L : s.leaves) all.push_back(&L);
     rc = upload_bathy(c, s, all);
@@ -1133,17 +1226,16 @@ int gf_set_state(gf_ctx *c, int32_t scen, const double *in)
     const Scen &s = c->sc[(size_t)scen];
     const size_t MM = (size_t)c->m * c->m;
     const int cur = c->hs[(size_t)scen].cur;
-    // stage everything, queue the copies, wait once
-    std::vector<char> tmp(s.leaves.size() * 3 * MM * c->es);
-    for (size_t k = 0; k < s.leaves.size(); ++k)
-        for (int f = 0; f < 3; ++f) {
-            const double *src = in + (k * 3 + (size_t)f) * MM;
-            char *stage = tmp.data() + (k * 3 + (size_t)f) * MM * c->es;
-            if (c->prec == GF_FP32) to_real<float>(src, (float *)stage, MM);
-            else to_real<double>(src, (double *)stage, MM);
-            char *dev = (char *)c->q[cur] + ((size_t)f * fstride(c) + (size_t)s.leaves[k].slot * MM) * c->es;
-            HIPCHK(c, hipMemcpyAsync(dev, stage, MM * c->es, hipMemcpyHostToDevice, c->stream));
-        }
+    // convert on the host, one upload in leaf order, scattered to the slots
+    const size_t n = s.leaves.size();
+    std::vector<char> tmp(n * 3 * MM * c->es);
+    if (c->prec == GF_FP32) to_real<float>(in, (float *)tmp.data(), n * 3 * MM);
+    else to_real<double>(in, (double *)tmp.data(), n * 3 * MM);
+    rc = stage_slots(c, s, tmp.size());
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->d_sstage, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
+    rc = launch_state(c, 1, c->d_sstage, nullptr, (int)n, c->q[cur]);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->flags_dirty = true;
     return GF_OK;
@@ -1157,20 +1249,17 @@ int gf_get_state(gf_ctx *c, int32_t scen, double *out)
     const Scen &s = c->sc[(size_t)scen];
     const size_t MM = (size_t)c->m * c->m;
     const int cur = c->hs[(size_t)scen].cur;
-    // copy whole buffers once, then gather
-    std::vector<char> qh(3 * fstride(c) * c->es), bh(MM * (size_t)c->cap * c->es);
-    HIPCHK(c, hipMemcpyAsync(qh.data(), c->q[cur], qh.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(bh.data(), c->b, bh.size(), hipMemcpyDeviceToHost, c->stream));
+    // gathered on the device in leaf order, one download, widened on the host
+    const size_t n = s.leaves.size();
+    std::vector<char> tmp(n * 4 * MM * c->es);
+    rc = stage_slots(c, s, tmp.size());
+    if (rc) return rc;
+    rc = launch_state(c, 0, c->q[cur], c->b, (int)n, c->d_sstage);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), c->d_sstage, tmp.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (size_t k = 0; k < s.leaves.size(); ++k) {
-        const size_t slot = (size_t)s.leaves[k].slot;
-        for (int f = 0; f < 4; ++f) {
-            double *dst = out + (k * 4 + (size_t)f) * MM;
-            const char *src = f < 3 ? qh.data() + ((size_t)f * fstride(c) + slot * MM) * c->es : bh.data() + slot * MM * c->es;
-            if (c->prec == GF_FP32) from_real<float>((const float *)src, dst, MM);
-            else from_real<double>((const double *)src, dst, MM);
-        }
-    }
+    if (c->prec == GF_FP32) from_real<float>((const float *)tmp.data(), out, n * 4 * MM);
+    else from_real<double>((const double *)tmp.data(), out, n * 4 * MM);
     return GF_OK;
 }
 

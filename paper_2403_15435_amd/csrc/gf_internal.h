@@ -125,6 +125,8 @@ struct RefluxArgsBase {
                                     hipStream_t s);                                                 \
     hipError_t gf_launch_transfer_##SFX(const void *tasks, int n, const gf::ScenDev *scen, R *q0, R *q1, \
                                         const R *b, int64_t cap, double tau, int m, hipStream_t s);       \
+    hipError_t gf_launch_state_##SFX(int kind, const R *a, const R *b, const int32_t *slots, int n,      \
+                                     int64_t fs, R *out, int m, hipStream_t s);                       \
     hipError_t gf_launch_bathy_##SFX(const R *staged, const int32_t *slots, int n, R *b, R *bg, int m,  \
                                      hipStream_t s);                                                  \
     hipError_t gf_launch_ghost_##SFX(const gf::StepArgs<R> &a, const int32_t *items, int n, R *ghost, int m, \
