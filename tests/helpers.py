@@ -62,3 +62,36 @@ def init_oracle(o, sc, precision="f64"):
         o.set_field(k, 0, np.asarray(h, dtype=np.float64))
         o.set_field(k, 1, np.asarray(hu, dtype=np.float64))
         o.set_field(k, 2, np.asarray(hv, dtype=np.float64))
+
+
+def _dilate(mask, r):
+    pad = np.pad(mask, r, mode="edge")
+    out = np.zeros_like(mask)
+    for dj in range(2 * r + 1):
+        for di in range(2 * r + 1):
+            out |= pad[dj:dj + mask.shape[0], di:di + mask.shape[1]]
+    return out
+
+
+def check_fp32(sc, leaves, g, o, level):
+    """Max relative h error away from fronts and max absolute error at front
+    cells, on the mesh projected to `level`.  A cell is at a front when a cell
+    of depth <= 1e-2 m (in either solution) lies within 2 cells of the cell's
+    own level (a 5x5 neighbourhood on a uniform mesh)."""
+    Ho = to_finest(sc, leaves, o, 0, level)
+    Hg = to_finest(sc, leaves, g, 0, level)
+    shallow = (Ho <= 1e-2) | (Hg <= 1e-2)
+    lvl = np.full(Ho.shape, level)
+    m = sc.m
+    for t, l, ix, iy in np.asarray(leaves):
+        rr = 1 << (level - l)
+        PI = (t % sc.mi) * (1 << l) + ix
+        PJ = (t // sc.mi) * (1 << l) + iy
+        lvl[PJ * m * rr:(PJ + 1) * m * rr, PI * m * rr:(PI + 1) * m * rr] = l
+    near = np.zeros_like(shallow)
+    for l in np.unique(lvl):
+        near |= _dilate(shallow, 2 << (level - l)) & (lvl == l)
+    away = ~near
+    rel = np.abs(Hg - Ho)[away] / Ho[away] if away.any() else np.zeros(1)
+    front = np.abs(Hg - Ho)[near] if near.any() else np.zeros(1)
+    return float(rel.max()), float(front.max())

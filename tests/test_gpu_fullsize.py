@@ -1,0 +1,134 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark
+times (512-thread step kernel on the resident persistent grid):
+
+- the uniform 2048^2 reservoir: FP64 bit for bit and FP32 within its bar
+  against the CPU oracle over 10 steps of the oracle's lengths;
+- the 256-scenario ensemble in one launch: sampled scenarios bit for bit
+  against their own oracle runs;
+- the 25k-leaf AMR valley, too large for the oracle: properties that hold
+  at any size (fused and plain paths equal bit for bit through a regrid,
+  the volume budget closed)."""
+import numpy as np
+import pytest
+
+import paper_2403_15435_amd as gf
+from paper_2403_15435_amd import inputs
+from helpers import _dilate, init_oracle, to_finest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _bench_shape(ctx):
+    ctx.set_step_threads(512)
+    ctx.set_schedule(-1)
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_reservoir_2048_against_oracle(orc, prec):
+    sc = inputs.reservoir_fractal(level=6, m=32, L=10000.0, seed=2, radius=400.0, h_res=20.0, manning_n=0.033)
+    f32 = prec == gf.GF_FP32
+    o = orc.Oracle(sc, cfl_desired=0.9)
+    if f32:
+        o.set_bathy_f32(True)
+    init_oracle(o, sc, "f32" if f32 else "f64")
+    ctx = gf.Context([sc], precision=prec, max_patches=4096)
+    _bench_shape(ctx)
+    st0 = o.state()
+    ctx.set_state(0, (st0.astype(np.float32).astype(np.float64) if f32 else st0)[:, :3])
+    nu, dts = o.advance(10, return_dt=True)
+    print(f"2048^2 reservoir ({'fp32' if f32 else 'fp64'}): oracle 10 steps to t = {o.t:.3f} s", flush=True)
+    ctx.step(len(dts), dts)
+    g, r = ctx.state(0), o.state()
+    if not f32:
+        assert np.array_equal(g[:, :3], r[:, :3])
+        return
+    # FP32: the difference from FP64 starts at the wet/dry front (wet/dry
+    # decisions and tiny depths there) and travels inward with the bore, about
+    # a cell per step; the front zone is the cells within 6 cells of a shallow
+    # cell after these 10 steps.  Bars: 1e-3 m absolute on the wet/dry cells
+    # themselves, 2e-5 relative beyond the zone, and a decaying profile between.
+    lv = o.leaves()
+    Ho, Hg = to_finest(sc, lv, r, 0, 6), to_finest(sc, lv, g, 0, 6)
+    shallow = (Ho <= 1e-2) | (Hg <= 1e-2)
+    rel = np.where(~shallow, np.abs(Hg - Ho) / np.where(shallow, 1.0, Ho), 0.0)
+    near1 = _dilate(shallow, 1)
+    zone = _dilate(shallow, 6)
+    prof, prev = [], shallow.copy()
+    for d in range(1, 9):
+        ring = _dilate(shallow, d) & ~prev
+        prev |= ring
+        prof.append(float(rel[ring].max()) if ring.any() else 0.0)
+    print("  fp32 max rel by distance to the front (cells 1..8): " + " ".join(f"{x:.1e}" for x in prof), flush=True)
+    abs_wetdry = float(np.abs(Hg - Ho)[near1].max())
+    rel_away = float(rel[~zone].max())
+    print(f"  fp32: abs at wet/dry cells {abs_wetdry:.3e} m, rel beyond 6 cells {rel_away:.3e}", flush=True)
+    assert abs_wetdry <= 1e-3
+    assert rel_away <= 2e-5
+    assert prof[-1] <= 1e-5 and prof[-1] < prof[0]
+
+
+def test_ensemble_256_sampled_scenarios_against_oracle(orc):
+    scs = inputs.ensemble_dambreaks()
+    cap = sum(int(round((s.x1 - s.x0) / 10.0)) ** 2 // 1024 for s in scs)
+    ctx = gf.Context(scs, precision=gf.GF_FP64, max_patches=cap)
+    _bench_shape(ctx)
+    rng = np.random.default_rng(42)
+    picks = sorted(rng.choice(len(scs), size=4, replace=False).tolist())
+    oracles = {}
+    for k in range(len(scs)):
+        if k in picks:
+            # the sampled scenarios start from the oracle's own initial state
+            o = orc.Oracle(scs[k])
+            init_oracle(o, scs[k])
+            ctx.set_state(k, o.state()[:, :3])
+            oracles[k] = o
+        else:
+            ctx.set_initial(k)
+    st = ctx.step(20)
+    assert st.steps == 20 * len(scs)
+    for k in picks:
+        o = oracles[k]
+        o.advance(20)
+        t, dt, steps, rej = ctx.time(k)
+        assert (steps, rej, t, dt) == (o.steps, o.rejected, o.t, o.dt), k
+        assert np.array_equal(ctx.state(k)[:, :3], o.state()[:, :3]), k
+        print(f"ensemble member {k} ({int(scs[k].x1 / 10)}^2 cells): bit-identical after 20 steps", flush=True)
+
+
+def test_valley_25k_leaves_fused_equals_plain_through_regrid():
+    sc = inputs.v_valley()
+    a = gf.Context([sc], precision=gf.GF_FP64, max_patches=40000)
+    a.set_initial(0)
+    for _ in range(sc.max_level - sc.min_level):
+        a.tag()
+        a.regrid(None)
+        a.set_initial(0)
+    a.set_time(0, 4000.0)
+    leaves, state = a.leaves(0), a.state(0)
+    print(f"valley mesh: {leaves.shape[0]} leaves", flush=True)
+    assert leaves.shape[0] > 20000
+    b = gf.Context([sc], precision=gf.GF_FP64, max_patches=40000)
+    b.set_leaves(0, leaves)
+    b.set_state(0, state[:, :3])
+    b.set_time(0, 4000.0)
+    _bench_shape(a)
+    m0 = a.mass(0)
+    for ctx, plain in ((a, False), (b, True)):
+        ctx.step(4, plain=plain)
+        ctx.tag()
+        ctx.regrid(None)
+        ctx.step(4, plain=plain)
+    assert np.array_equal(a.leaves(0), b.leaves(0))
+    assert a.time(0) == b.time(0)
+    assert np.array_equal(a.state(0), b.state(0))
+    M = a.mass(0)
+    assert np.array_equal(M, b.mass(0))
+    assert abs((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) <= 1e-12 * m0[0]
+    assert M[2] - m0[2] != 0.0
