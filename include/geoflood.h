@@ -66,6 +66,23 @@ typedef struct {
     double tag_h_refine;         /* depth refine threshold H_r [m] */
     double tag_eta_refine;       /* free-surface difference threshold E_r [m] */
     double t_end;                /* stop time; steps are truncated to reach it */
+    /* Further refinement criteria of Section 4.1.  A wet cell also meets the
+     * refine criteria where its speed max(|u|, |v|) exceeds tag_u_refine
+     * (tested as max(|hu|, |hv|) > U h) or max(|hu|, |hv|) exceeds
+     * tag_q_refine (velocity-depth product); 0 turns either off.  Arrays are
+     * copied at gf_create and may be freed after it. */
+    double tag_u_refine;         /* speed threshold [m/s], >= 0 */
+    double tag_q_refine;         /* velocity-depth product threshold [m^2/s], >= 0 */
+    int32_t n_regions;           /* flood-source regions, <= 4 */
+    const double *regions;       /* n_regions x 6: x0 y0 x1 y1 min_level max_level; a leaf
+                                  * overlapping a region is refined below its min level,
+                                  * never refined at or above its max level, and never
+                                  * coarsened at or below its min level (largest over
+                                  * the regions it overlaps) */
+    int32_t n_grades;            /* flow grades, <= 4 */
+    const double *grades;        /* n_grades x 3: quantity (0 depth, 1 speed), threshold,
+                                  * level; a leaf with a wet cell above a grade's
+                                  * threshold is taken to the largest such level */
 } gf_scenario_desc;
 
 typedef struct {
@@ -153,10 +170,13 @@ int gf_step(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *
 int gf_step_plain(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
 
 /* Refinement flags of every leaf of every scenario, concatenated in scenario
- * then leaf order: +1 refine, -1 coarsen, 0 keep (the depth, free-surface
- * gradient and advancing-front criteria of Section 4.1, with halved thresholds
- * for coarsening).  Decided in FP64 with + - and compares only.  `flags_out`
- * is nullable (the flags are kept for gf_regrid). */
+ * then leaf order: +1 refine, -1 coarsen, 0 keep (Section 4.1).  In order:
+ * the cell criteria (depth, free-surface gradient, advancing front, speed,
+ * velocity-depth product) refine at their thresholds and keep at half of
+ * them, else the leaf coarsens; flow grades that hold set the leaf's level;
+ * flood-source regions force or cap it; the scenario's level limits apply
+ * last.  Decided in FP64 with * + - and compares only.  `flags_out` is
+ * nullable (the flags are kept for gf_regrid). */
 int gf_tag(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
 
 /* Apply flags (NULL: those of the last gf_tag): refine, close under 2:1

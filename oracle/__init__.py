@@ -61,6 +61,7 @@ def lib():
         L.orc_set_bathy_f32.argtypes = [C.c_void_p, C.c_int]
         L.orc_mass.argtypes = [C.c_void_p, _dp]
         L.orc_tag.argtypes = [C.c_void_p, C.POINTER(C.c_byte)]
+        L.orc_set_tag_rules.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, _dp]
         L.orc_regrid.argtypes = [C.c_void_p, C.POINTER(C.c_byte)]
         L.orc_time.argtypes = [C.c_void_p]
         L.orc_time.restype = C.c_double
@@ -121,6 +122,10 @@ class Oracle:
         nh = len(sc.hydro) if sc.hydro else 0
         L = lib()
         self._p = L.orc_create(_d(dp), ip.ctypes.data_as(_ip), _d(hy), nh)
+        rg = np.asarray(sc.regions if sc.regions else [(0.0,) * 6], dtype=np.float64).reshape(-1)
+        gr = np.asarray(sc.grades if sc.grades else [(0.0,) * 3], dtype=np.float64).reshape(-1)
+        L.orc_set_tag_rules(self._p, sc.tag_u_refine, sc.tag_q_refine, len(sc.regions) if sc.regions else 0, _d(rg),
+                            len(sc.grades) if sc.grades else 0, _d(gr))
         dem = np.ascontiguousarray(sc.dem, dtype=np.float64)
         rc = L.orc_set_dem(self._p, _d(dem), dem.shape[1], dem.shape[0], sc.dem_level)
         if rc != 0:

@@ -69,6 +69,15 @@ typedef struct {
     /* scenario */
     double x0, y0, x1, y1, g, tau, manning, cfl_desired, cfl_max;
     double inflow_lo, inflow_hi, tag_h, tag_eta, t_end;
+    /* further refinement criteria of Section 4.1 (reading R20'): velocity,
+       velocity-depth product (0: off), flood-source regions, flow grades */
+    double tag_u, tag_q;
+    int n_regions, n_grades;
+    double region[4][4];          /* x0 y0 x1 y1 */
+    int region_level[4][2];       /* min, max */
+    int grade_quantity[4];        /* 0 depth, 1 speed */
+    double grade_threshold[4];
+    int grade_level[4];
     int mi, mj, m, min_level, max_level, bc[4], inflow_side;
     int n_hydro;
     double hydro_t[64], hydro_q[64];
@@ -1406,13 +1415,21 @@ void orc_mass(const orc_sim *s, double out[3])
 /* refinement criteria (Section 4.1 list; readings R20-R22)                    */
 /* ------------------------------------------------------------------------ */
 
-static int cell_criterion(const orc_sim *s, const leaf_t *L, int i, int j, double Hr, double Er)
+static int cell_criterion(const orc_sim *s, const leaf_t *L, int i, int j, double Hr, double Er, double Ur, double Qr)
 {
     int m = s->m;
     double h = L->q[0][G(s, i, j)], b = L->b[G(s, i, j)], ex, ey, gmax;
     const double *H = L->q[0], *B = L->b;
     if (h > Hr) return 1;
     if (!(h > s->tau)) return 0;
+    {
+        /* velocity criterion max(|u|, |v|) > U_r, written as |hu| > U_r h;
+           velocity-depth product max(|hu|, |hv|) > Q_r */
+        const double hu = fabs(L->q[1][G(s, i, j)]), hv = fabs(L->q[2][G(s, i, j)]);
+        const double mq = hu > hv ? hu : hv;
+        if (Ur > 0.0 && mq > Ur * h) return 1;
+        if (Qr > 0.0 && mq > Qr) return 1;
+    }
     if (i == 0) ex = (H[G(s, 1, j)] - H[G(s, 0, j)]) + (B[G(s, 1, j)] - B[G(s, 0, j)]);
     else if (i == m - 1) ex = (H[G(s, m - 1, j)] - H[G(s, m - 2, j)]) + (B[G(s, m - 1, j)] - B[G(s, m - 2, j)]);
     else ex = 0.5 * ((H[G(s, i + 1, j)] - H[G(s, i - 1, j)]) + (B[G(s, i + 1, j)] - B[G(s, i - 1, j)]));
@@ -1434,20 +1451,89 @@ static int cell_criterion(const orc_sim *s, const leaf_t *L, int i, int j, doubl
     return 0;
 }
 
+/* flow grade g holds for the leaf: a wet cell whose depth (quantity 0) or
+   speed max(|u|, |v|) (quantity 1, as max(|hu|, |hv|) > threshold h) exceeds
+   the threshold */
+static int grade_holds(const orc_sim *s, const leaf_t *L, int g)
+{
+    int m = s->m, i, j;
+    for (j = 0; j < m; ++j)
+        for (i = 0; i < m; ++i) {
+            const double h = L->q[0][G(s, i, j)];
+            if (!(h > s->tau)) continue;
+            if (s->grade_quantity[g] == 0) {
+                if (h > s->grade_threshold[g]) return 1;
+            } else {
+                const double hu = fabs(L->q[1][G(s, i, j)]), hv = fabs(L->q[2][G(s, i, j)]);
+                if ((hu > hv ? hu : hv) > s->grade_threshold[g] * h) return 1;
+            }
+        }
+    return 0;
+}
+
+/* Flags per leaf (Section 4.1; readings R20, R20'):
+   1. refine if a cell meets the criteria at their thresholds, keep if one
+      meets them at half; coarsen otherwise;
+   2. flow grades: where any holds, the leaf is taken to the largest level of
+      those that hold (refine below it, coarsen above it);
+   3. flood-source regions overlapping the leaf: refinement forced below
+      their largest minimum level, refused at or above their largest maximum
+      level, coarsening refused at or below the minimum;
+   4. the scenario's level limits. */
 void orc_tag(const orc_sim *s, signed char *flags)
 {
-    int m = s->m, k, i, j;
+    int m = s->m, k, i, j, g, r;
     for (k = 0; k < s->n_leaves; ++k) {
         const leaf_t *L = &s->leaves[k];
-        int ref = 0, keep = 0;
+        int ref = 0, keep = 0, f, target = -1, lo = -1, hi = -1;
         for (j = 0; j < m; ++j)
             for (i = 0; i < m; ++i) {
-                if (!ref && cell_criterion(s, L, i, j, s->tag_h, s->tag_eta)) ref = 1;
-                if (!keep && cell_criterion(s, L, i, j, 0.5 * s->tag_h, 0.5 * s->tag_eta)) keep = 1;
+                if (!ref && cell_criterion(s, L, i, j, s->tag_h, s->tag_eta, s->tag_u, s->tag_q)) ref = 1;
+                if (!keep && cell_criterion(s, L, i, j, 0.5 * s->tag_h, 0.5 * s->tag_eta, 0.5 * s->tag_u, 0.5 * s->tag_q)) keep = 1;
             }
-        if (ref && L->level < s->max_level) flags[k] = 1;
-        else if (!keep && L->level > s->min_level) flags[k] = -1;
-        else flags[k] = 0;
+        f = ref ? 1 : (keep ? 0 : -1);
+        for (g = 0; g < s->n_grades; ++g)
+            if (grade_holds(s, L, g) && s->grade_level[g] > target) target = s->grade_level[g];
+        if (target >= 0) f = L->level < target ? 1 : (L->level > target ? -1 : 0);
+        {
+            const double dx = DX(s, L->level), dy = DY(s, L->level);
+            const double xa = s->x0 + (double)(L->PI * m) * dx, xb = s->x0 + (double)((L->PI + 1) * m) * dx;
+            const double ya = s->y0 + (double)(L->PJ * m) * dy, yb = s->y0 + (double)((L->PJ + 1) * m) * dy;
+            for (r = 0; r < s->n_regions; ++r) {
+                if (!(xa < s->region[r][2] && xb > s->region[r][0] && ya < s->region[r][3] && yb > s->region[r][1])) continue;
+                if (s->region_level[r][0] > lo) lo = s->region_level[r][0];
+                if (s->region_level[r][1] > hi) hi = s->region_level[r][1];
+            }
+        }
+        if (lo >= 0 && L->level < lo) f = 1;
+        if (hi >= 0 && f == 1 && L->level >= hi) f = 0;
+        if (lo >= 0 && f == -1 && L->level <= lo) f = 0;
+        if (f == 1 && L->level >= s->max_level) f = 0;
+        if (f == -1 && L->level <= s->min_level) f = 0;
+        flags[k] = (signed char)f;
+    }
+}
+
+/* velocity and velocity-depth thresholds (0: off); regions: 6 values each
+   (x0 y0 x1 y1 min_level max_level); grades: 3 values each (quantity,
+   threshold, level); at most 4 of each */
+void orc_set_tag_rules(orc_sim *s, double ur, double qr, int n_regions, const double *regions, int n_grades,
+                       const double *grades)
+{
+    int k;
+    s->tag_u = ur;
+    s->tag_q = qr;
+    s->n_regions = n_regions < 0 ? 0 : (n_regions > 4 ? 4 : n_regions);
+    for (k = 0; k < s->n_regions; ++k) {
+        s->region[k][0] = regions[6 * k]; s->region[k][1] = regions[6 * k + 1];
+        s->region[k][2] = regions[6 * k + 2]; s->region[k][3] = regions[6 * k + 3];
+        s->region_level[k][0] = (int)regions[6 * k + 4]; s->region_level[k][1] = (int)regions[6 * k + 5];
+    }
+    s->n_grades = n_grades < 0 ? 0 : (n_grades > 4 ? 4 : n_grades);
+    for (k = 0; k < s->n_grades; ++k) {
+        s->grade_quantity[k] = (int)grades[3 * k];
+        s->grade_threshold[k] = grades[3 * k + 1];
+        s->grade_level[k] = (int)grades[3 * k + 2];
     }
 }
 

@@ -27,7 +27,9 @@ class gf_scenario_desc(C.Structure):
                 ("manning_n", C.c_double), ("bc", C.c_int32 * 4), ("inflow_side", C.c_int32),
                 ("inflow_lo", C.c_double), ("inflow_hi", C.c_double), ("hydro", C.POINTER(C.c_double)),
                 ("n_hydro", C.c_int32), ("tag_h_refine", C.c_double), ("tag_eta_refine", C.c_double),
-                ("t_end", C.c_double)]
+                ("t_end", C.c_double), ("tag_u_refine", C.c_double), ("tag_q_refine", C.c_double),
+                ("n_regions", C.c_int32), ("regions", C.POINTER(C.c_double)),
+                ("n_grades", C.c_int32), ("grades", C.POINTER(C.c_double))]
 
 
 class gf_config(C.Structure):
@@ -167,6 +169,12 @@ class Context:
             d.n_hydro = len(sc.hydro) if sc.hydro else 0
             d.tag_h_refine, d.tag_eta_refine = sc.tag_h_refine, sc.tag_eta_refine
             d.t_end = sc.t_end
+            d.tag_u_refine, d.tag_q_refine = sc.tag_u_refine, sc.tag_q_refine
+            rg = np.ascontiguousarray(np.asarray(sc.regions if sc.regions else [(0.0,) * 6], dtype=np.float64).reshape(-1))
+            gr = np.ascontiguousarray(np.asarray(sc.grades if sc.grades else [(0.0,) * 3], dtype=np.float64).reshape(-1))
+            self._hydro += [rg, gr]
+            d.n_regions, d.regions = (len(sc.regions) if sc.regions else 0), _dptr(rg)
+            d.n_grades, d.grades = (len(sc.grades) if sc.grades else 0), _dptr(gr)
         if max_patches is None:
             max_patches = 0
             for sc in self.scenarios:

@@ -143,6 +143,7 @@ struct Scen {
     std::vector<std::vector<double>> pyr;   // levels 0..dem_level
     std::vector<Leaf> leaves;
     LeafMap map;                            // key -> leaf index
+    TagRules rules{};
     double clamp_base = 0.0, bnd_base = 0.0;
 };
 
@@ -192,8 +193,8 @@ struct gf_ctx {
     ScenDev *d_scen = nullptr;
     unsigned *d_counter = nullptr;
     int8_t *d_flags = nullptr;
-    double *d_thr = nullptr, *d_mass = nullptr;
-    int32_t *d_lev = nullptr;
+    double *d_mass = nullptr;
+    TagRules *d_rules = nullptr;
     XferTaskH *d_xfer = nullptr;
     int64_t xfer_cap = 0;
     // host mirrors
@@ -984,6 +985,46 @@ static thread_local char g_create_err[512] = "null context";
 
 const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err; }
 
+static bool whole_level(double v) { return v >= 0.0 && v <= 30.0 && v == (double)(int)v; }
+
+// Speed and velocity-depth thresholds non-negative; regions non-empty boxes
+// with 0 <= min level <= max level; grades of quantity 0 or 1 with a
+// non-negative threshold and a level >= 0.
+static bool tag_rules_valid(const gf_scenario_desc &d)
+{
+    if (!(d.tag_u_refine >= 0.0) || !(d.tag_q_refine >= 0.0)) return false;
+    if (d.n_regions < 0 || d.n_regions > kMaxRegions || (d.n_regions > 0 && !d.regions)) return false;
+    if (d.n_grades < 0 || d.n_grades > kMaxGrades || (d.n_grades > 0 && !d.grades)) return false;
+    for (int r = 0; r < d.n_regions; ++r) {
+        const double *v = d.regions + 6 * r;
+        if (!(v[2] > v[0]) || !(v[3] > v[1]) || !whole_level(v[4]) || !whole_level(v[5]) || v[5] < v[4]) return false;
+    }
+    for (int g = 0; g < d.n_grades; ++g) {
+        const double *v = d.grades + 3 * g;
+        if (!(v[0] == 0.0 || v[0] == 1.0) || !(v[1] >= 0.0) || !whole_level(v[2])) return false;
+    }
+    return true;
+}
+
+static TagRules make_tag_rules(const gf_scenario_desc &d)
+{
+    TagRules T{};
+    T.h = d.tag_h_refine; T.eta = d.tag_eta_refine; T.u = d.tag_u_refine; T.q = d.tag_q_refine;
+    T.lmin = d.min_level; T.lmax = d.max_level;
+    T.n_regions = d.n_regions; T.n_grades = d.n_grades;
+    for (int r = 0; r < d.n_regions; ++r) {
+        for (int k = 0; k < 4; ++k) T.region[r][k] = d.regions[6 * r + k];
+        T.region_lev[r][0] = (int32_t)d.regions[6 * r + 4];
+        T.region_lev[r][1] = (int32_t)d.regions[6 * r + 5];
+    }
+    for (int g = 0; g < d.n_grades; ++g) {
+        T.grade_qty[g] = (int32_t)d.grades[3 * g];
+        T.grade_thr[g] = d.grades[3 * g + 1];
+        T.grade_lev[g] = (int32_t)d.grades[3 * g + 2];
+    }
+    return T;
+}
+
 int gf_create(const gf_config *cfg, gf_ctx **out)
 {
     if (!cfg || !out) return GF_E_INVALID;
@@ -1008,7 +1049,7 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
         const gf_scenario_desc &d = cfg->scen[i];
         if (d.mi <= 0 || d.mj <= 0 || d.min_level < 0 || d.max_level < d.min_level || d.max_level > 14 ||
             !(d.x1 > d.x0) || !(d.y1 > d.y0) || d.n_hydro < 0 || d.n_hydro > kMaxHydro ||
-            (d.n_hydro > 0 && !d.hydro)) {
+            (d.n_hydro > 0 && !d.hydro) || !tag_rules_valid(d)) {
             delete c;
             return GF_E_INVALID;
         }
@@ -1016,6 +1057,9 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
         s.d = d;
         s.hydro.assign(d.hydro ? d.hydro : nullptr, d.hydro ? d.hydro + 2 * d.n_hydro : nullptr);
         s.d.hydro = nullptr;
+        s.rules = make_tag_rules(d);
+        s.d.regions = nullptr;
+        s.d.grades = nullptr;
         ScenDev &h = c->hs[(size_t)i];
         h.t = 0.0; h.dt = 0.0; h.t_end = d.t_end; h.manning_n = d.manning_n;
         h.inflow_lo = d.inflow_lo; h.inflow_hi = d.inflow_hi; h.inflow_side = d.inflow_side;
@@ -1045,19 +1089,14 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
          alloc((void **)&c->dry[1], (size_t)c->cap);
     ok = ok && alloc((void **)&c->d_wet, sizeof(int32_t) * (size_t)c->cap) && alloc((void **)&c->d_wet_count, 64);
     ok = ok && alloc((void **)&c->d_dstab, (size_t)c->cap) && alloc((void **)&c->d_stats, 64);
-    ok = ok && alloc((void **)&c->d_thr, sizeof(double) * 2 * c->sc.size()) && alloc((void **)&c->d_lev, sizeof(int32_t) * 2 * c->sc.size());
+    ok = ok && alloc((void **)&c->d_rules, sizeof(TagRules) * c->sc.size());
     if (!ok) {
         gf_destroy(c);
         return GF_E_NOMEM;
     }
-    std::vector<double> thr;
-    std::vector<int32_t> lev;
-    for (auto &s : c->sc) {
-        thr.push_back(s.d.tag_h_refine); thr.push_back(s.d.tag_eta_refine);
-        lev.push_back(s.d.min_level); lev.push_back(s.d.max_level);
-    }
-    if (hipMemcpy(c->d_thr, thr.data(), sizeof(double) * thr.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_lev, lev.data(), sizeof(int32_t) * lev.size(), hipMemcpyHostToDevice) != hipSuccess ||
+    std::vector<TagRules> rules;
+    for (auto &s : c->sc) rules.push_back(s.rules);
+    if (hipMemcpy(c->d_rules, rules.data(), sizeof(TagRules) * rules.size(), hipMemcpyHostToDevice) != hipSuccess ||
         push_scen(c) != GF_OK) {
         gf_destroy(c);
         return GF_E_HIP;
@@ -1072,7 +1111,7 @@ void gf_destroy(gf_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     void *ps[] = {c->q[0], c->q[1], c->b, c->bg, c->reg, c->ghost, c->cacc[0], c->cacc[1], c->bacc[0], c->bacc[1],
-                  c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_thr, c->d_mass, c->d_lev, c->d_xfer,
+                  c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_rules, c->d_mass, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
                   c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats,
                   c->d_sstage, c->d_sslots};
@@ -1428,10 +1467,10 @@ int gf_tag(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n)
     hipError_t e;
     if (c->prec == GF_FP32)
         e = gf_launch_tag_f32(c->d_desc, nw, c->d_scen, (const float *)c->q[0], (const float *)c->q[1], (const float *)c->b,
-                              c->cap, c->d_thr, c->d_lev, c->cfg.dry_tol, c->d_flags, c->m, c->stream);
+                              c->cap, c->d_rules, c->cfg.dry_tol, c->d_flags, c->m, c->stream);
     else
         e = gf_launch_tag_f64(c->d_desc, nw, c->d_scen, (const double *)c->q[0], (const double *)c->q[1], (const double *)c->b,
-                              c->cap, c->d_thr, c->d_lev, c->cfg.dry_tol, c->d_flags, c->m, c->stream);
+                              c->cap, c->d_rules, c->cfg.dry_tol, c->d_flags, c->m, c->stream);
     if (e != hipSuccess) return fail(c, GF_E_HIP, "tag launch: %s", hipGetErrorString(e));
     c->last_flags.resize((size_t)nw);
     if (nw) HIPCHK(c, hipMemcpyAsync(c->last_flags.data(), c->d_flags, (size_t)nw, hipMemcpyDeviceToHost, c->stream));

@@ -62,6 +62,19 @@ struct ScenDev {
     unsigned long long smax_bits;  // max |s|/dx of the running attempt (double bits)
 };
 
+// Refinement rules of one scenario (Section 4.1): thresholds of the cell
+// criteria, flood-source regions and flow grades.
+constexpr int kMaxRegions = 4, kMaxGrades = 4;
+struct TagRules {
+    double h, eta, u, q;              // depth, free surface, speed, velocity-depth (u, q: 0 off)
+    double region[kMaxRegions][4];    // x0 y0 x1 y1
+    double grade_thr[kMaxGrades];
+    int32_t lmin, lmax, n_regions, n_grades;
+    int32_t region_lev[kMaxRegions][2];  // min, max level inside
+    int32_t grade_qty[kMaxGrades];    // 0 depth, 1 speed
+    int32_t grade_lev[kMaxGrades];
+};
+
 template <typename R>
 struct StepArgs {
     const PatchDesc *desc;
@@ -118,8 +131,8 @@ struct RefluxArgsBase {
                                       hipStream_t s);                                               \
     hipError_t gf_launch_tag_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,         \
                                    const R *q0, const R *q1, const R *b, int64_t cap,              \
-                                   const double *thr, const int32_t *lev_limits, double tau64,     \
-                                   int8_t *flags, int m, hipStream_t s);                           \
+                                   const gf::TagRules *rules, double tau64, int8_t *flags, int m,  \
+                                   hipStream_t s);                                                 \
     hipError_t gf_launch_mass_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,        \
                                     const R *q0, const R *q1, int64_t cap, double *out, int m,     \
                                     hipStream_t s);                                                 \

@@ -162,6 +162,10 @@ class Scenario:
     tag_h_refine: float = 0.1
     tag_eta_refine: float = 0.05
     t_end: float = 1e300
+    tag_u_refine: float = 0.0              # speed threshold [m/s] (0: off)
+    tag_q_refine: float = 0.0              # velocity-depth product threshold [m^2/s] (0: off)
+    regions: Optional[List[Tuple[float, float, float, float, int, int]]] = None  # x0 y0 x1 y1 min max
+    grades: Optional[List[Tuple[int, float, int]]] = None                        # quantity threshold level
     dem: Optional[np.ndarray] = None       # node values [ny][nx] at level dem_level corners
     dem_level: int = 0
     init_level: int = 0

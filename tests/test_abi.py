@@ -40,3 +40,43 @@ def test_version_and_null_context():
     assert L.gf_profile_patches(None, None, None) == gf.GF_E_INVALID
     assert L.gf_run(None, 1, 0, 4, 16, None) == gf.GF_E_INVALID
     assert L.gf_net_collect(None, 16, 4, None, None, 0, None) == gf.GF_E_INVALID
+
+
+@pytest.mark.parametrize("bad", ["u", "q", "n_regions", "region_box", "region_levels", "region_fraction",
+                                 "n_grades", "grade_quantity", "grade_threshold", "grade_level", "null_regions"])
+def test_create_rejects_invalid_refinement_rules(bad):
+    """Rules are checked before anything touches the device."""
+    import paper_2403_15435_amd as gf
+    L = gf.load()
+    regions = (ctypes.c_double * 30)(*([10.0, 10.0, 20.0, 20.0, 1.0, 2.0] * 5))
+    grades = (ctypes.c_double * 15)(*([0.0, 0.5, 1.0] * 5))
+    d = gf.gf_scenario_desc(x0=0.0, y0=0.0, x1=100.0, y1=100.0, mi=1, mj=1, min_level=0, max_level=2,
+                            manning_n=0.0, inflow_side=-1, tag_h_refine=0.1, tag_eta_refine=0.05, t_end=1.0,
+                            n_regions=1, regions=regions, n_grades=1, grades=grades)
+    if bad == "u":
+        d.tag_u_refine = -1.0
+    elif bad == "q":
+        d.tag_q_refine = float("nan")
+    elif bad == "n_regions":
+        d.n_regions = 5
+    elif bad == "region_box":
+        regions[2] = 5.0                  # x1 < x0
+    elif bad == "region_levels":
+        regions[4], regions[5] = 3.0, 2.0  # min above max
+    elif bad == "region_fraction":
+        regions[4] = 1.5
+    elif bad == "n_grades":
+        d.n_grades = 5
+    elif bad == "grade_quantity":
+        grades[0] = 2.0
+    elif bad == "grade_threshold":
+        grades[1] = -0.5
+    elif bad == "grade_level":
+        grades[2] = -1.0
+    elif bad == "null_regions":
+        d.regions = None
+    cfg = gf.gf_config(precision=gf.GF_FP64, m=16, g=9.81, dry_tol=1e-4, cfl_desired=0.9, cfl_max=1.0, n_scen=1,
+                       scen=ctypes.pointer(d), max_patches=16, hip_stream=None)
+    out = ctypes.c_void_p()
+    assert L.gf_create(ctypes.byref(cfg), ctypes.byref(out)) == gf.GF_E_INVALID
+    assert not out.value

@@ -496,6 +496,114 @@ def test_random_flag_regrids_bit_exact(orc, seed):
     assert abs(ctx.mass(0)[0] - m0) <= 1e-12 * m0
 
 
+def _lake_case(orc, depths, mom=(), max_level=3, **kw):
+    """Four level-1 leaves of 16^2 cells, each a still pool of its own depth
+    over a flat bed, momentum planted at single cells (leaf, field, value)."""
+    sc = inputs.Scenario(name="tag2", x0=0.0, y0=0.0, x1=320.0, y1=320.0, mi=1, mj=1, m=16,
+                         min_level=0, max_level=max_level, manning_n=0.0, init_level=1, **kw)
+    sc.dem = np.zeros((17, 17)); sc.dem_level = 0
+    o = orc.Oracle(sc)
+    for k in range(4):
+        o.set_field(k, 0, np.full((16, 16), depths[k]))
+        o.set_field(k, 1, np.zeros((16, 16)))
+        o.set_field(k, 2, np.zeros((16, 16)))
+    for k, f, v in mom:
+        a = np.zeros((16, 16)); a[7, 9] = v
+        o.set_field(k, f, a)
+    return sc, o
+
+
+_RULE_CASES = {
+    "speed": ([0.04] * 4, [(0, 1, 0.048), (1, 2, -0.028), (2, 1, 0.018)], 3, dict(tag_u_refine=1.0)),
+    "velocity_depth": ([0.04] * 4, [(0, 1, -0.12), (1, 2, 0.06), (2, 1, 0.04)], 3, dict(tag_q_refine=0.1)),
+    "regions": ([0.04] * 4, [(2, 1, 0.08), (3, 1, 0.08)], 3,
+                dict(tag_u_refine=1.0, regions=[(10.0, 10.0, 20.0, 20.0, 2, 3), (200.0, 150.0, 210.0, 170.0, 1, 1),
+                                                (160.0, 170.0, 170.0, 180.0, 1, 1)])),
+    "region_above_max": ([0.04] * 4, [], 1, dict(regions=[(0.0, 0.0, 320.0, 320.0, 3, 3)])),
+    "grades": ([0.04, 0.03, 0.04, 0.03], [(1, 1, 0.018), (2, 2, -0.024), (3, 1, 0.009)], 3,
+               dict(tag_u_refine=0.5, grades=[(0, 0.035, 2), (1, 0.5, 0)])),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_RULE_CASES))
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_refinement_rules_on_planted_cells(orc, case, prec):
+    """Each further criterion of the tagger on hand-built leaves: the same
+    flags as the oracle (FP32: both take the state rounded to FP32)."""
+    depths, mom, lmax, kw = _RULE_CASES[case]
+    sc, o = _lake_case(orc, depths, mom, lmax, **kw)
+    st = o.state()
+    if prec == gf.GF_FP32:
+        st = st.astype(np.float32).astype(np.float64)
+        o.set_state(st)
+    fo = o.tag()
+    ctx = gf.Context([sc], precision=prec, max_patches=64)
+    ctx.set_state(0, st[:, :3])
+    fg = ctx.tag()
+    print(f"{case}: oracle {fo.tolist()} library {fg.tolist()}", flush=True)
+    assert np.array_equal(fo, fg)
+
+
+def _rules_dambreak():
+    """Dam break on fully wet fractal terrain with every further criterion on:
+    speed 1.6 m/s, velocity-depth 70 m^2/s, three flood-source regions, a
+    depth grade (90 m -> level 3) and a speed grade (3 m/s -> level 4); the
+    depth criterion off (1 km), free-surface threshold 2 m."""
+    sc = inputs.wet_dambreak(level=2, m=16, L=2000.0, seed=4, radius=400.0)
+    sc.min_level, sc.max_level = 1, 4
+    sc.tag_h_refine, sc.tag_eta_refine = 1e3, 2.0
+    sc.tag_u_refine, sc.tag_q_refine = 1.6, 70.0
+    sc.regions = [(0.0, 0.0, 300.0, 300.0, 2, 3), (1500.0, 100.0, 1900.0, 400.0, 1, 2),
+                  (700.0, 1300.0, 800.0, 1400.0, 1, 1)]
+    sc.grades = [(0, 90.0, 3), (1, 3.0, 4)]
+    return sc
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_refinement_rules_tag_regrid_bit_exact(orc, prec):
+    """Five tag / regrid / 8-step cycles of the rule-laden dam break: flags,
+    leaves and moved state equal to the oracle's (FP32: both sides take the
+    oracle state rounded to FP32 before each tag).  On the oracle, each rule
+    is checked to change some flag in some cycle."""
+    import copy
+    sc = _rules_dambreak()
+    f32 = prec == gf.GF_FP32
+    o = orc.Oracle(sc)
+    if f32:
+        o.set_bathy_f32(True)
+    init_oracle(o, sc, "f32" if f32 else "f64")
+    ctx = gf.Context([sc], precision=prec, max_patches=1024)
+    gpu_init_like(ctx, o, "f32" if f32 else "f64")
+    moved = {k: 0 for k in ("tag_u_refine", "tag_q_refine", "regions", "grades")}
+    for cycle in range(5):
+        if f32 and cycle > 0:
+            st32 = o.state().astype(np.float32).astype(np.float64)
+            o.set_state(st32)
+            ctx.set_state(0, st32[:, :3])
+        fo = o.tag()
+        fg = ctx.tag()
+        assert np.array_equal(fo, fg), cycle
+        lv, st = o.leaves(), o.state()
+        for k in moved:
+            sc2 = copy.copy(sc)
+            setattr(sc2, k, 0.0 if k.startswith("tag") else None)
+            o2 = orc.Oracle(sc2, leaves=lv)
+            if f32:
+                o2.set_bathy_f32(True)
+            o2.set_state(st)
+            moved[k] += int(np.count_nonzero(o2.tag() != fo))
+        assert o.regrid(fo) == ctx.regrid(fg)
+        assert np.array_equal(o.leaves(), ctx.leaves(0)), cycle
+        g, r = ctx.state(0), o.state()
+        assert np.array_equal(g[:, 3], r[:, 3])
+        if not f32:
+            assert np.array_equal(g[:, :3], r[:, :3]), cycle
+        nu, dts = o.advance(8, return_dt=True)
+        ctx.step(len(dts), dts)
+    print(f"flags changed by each rule over the cycles: {moved}", flush=True)
+    assert all(v > 0 for v in moved.values()), moved
+
+
 # ------------------------------------------------------------ invariants
 @pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
 def test_lake_at_rest_bit_exact(orc, prec):

@@ -270,6 +270,74 @@ def test_tagging_criteria(oracle_mod):
     assert fl[3] == -1         # dry everywhere
 
 
+def _tag_lake(oracle_mod, depths, mom=(), max_level=3, **kw):
+    """Four level-1 leaves of 16^2 cells over a flat bed, each a still pool of
+    its own depth (no gradient inside a leaf, no front), with momentum planted
+    at single cells: mom = [(leaf, field, value)]."""
+    sc = inputs.Scenario(name="tag2", x0=0.0, y0=0.0, x1=320.0, y1=320.0, mi=1, mj=1, m=16,
+                         min_level=0, max_level=max_level, manning_n=0.0, init_level=1, **kw)
+    sc.dem = np.zeros((17, 17)); sc.dem_level = 0
+    o = oracle_mod.Oracle(sc)
+    for k in range(4):
+        o.set_field(k, 0, np.full((16, 16), depths[k]))
+        o.set_field(k, 1, np.zeros((16, 16)))
+        o.set_field(k, 2, np.zeros((16, 16)))
+    for k, f, v in mom:
+        a = np.zeros((16, 16)); a[7, 9] = v
+        o.set_field(k, f, a)
+    return o.tag()
+
+
+def test_tagging_speed_criterion(oracle_mod):
+    """max(|u|, |v|) against U_r = 1 m/s at h = 0.04 m (below every depth
+    threshold): u = 1.2 refines, v = -0.7 keeps (above U_r/2), u = 0.45
+    coarsens; a leaf at rest coarsens."""
+    h = 0.04
+    fl = _tag_lake(oracle_mod, [h] * 4, [(0, 1, 1.2 * h), (1, 2, -0.7 * h), (2, 1, 0.45 * h)], tag_u_refine=1.0)
+    assert fl.tolist() == [1, 0, -1, -1]
+    # the same momenta with the criterion off: only the depth rule speaks
+    assert _tag_lake(oracle_mod, [h] * 4, [(0, 1, 1.2 * h), (1, 2, -0.7 * h)]).tolist() == [-1] * 4
+
+
+def test_tagging_velocity_depth_criterion(oracle_mod):
+    """max(|hu|, |hv|) against Q_r = 0.1 m^2/s, speed criterion off: hu =
+    -0.12 refines, hv = 0.06 keeps, hu = 0.04 (u = 1 m/s) coarsens."""
+    fl = _tag_lake(oracle_mod, [0.04] * 4, [(0, 1, -0.12), (1, 2, 0.06), (2, 1, 0.04)], tag_q_refine=0.1)
+    assert fl.tolist() == [1, 0, -1, -1]
+
+
+def test_tagging_flood_source_regions(oracle_mod):
+    """Leaves (Morton order) cover [0,160]^2, [160,320]x[0,160], [0,160]x
+    [160,320], [160,320]^2.  Region A inside leaf 0 with levels 2..3 forces
+    its refinement; region B across leaves 1 and 3 with levels 1..1 stops
+    the coarsening of leaf 1 (no criterion met) and the refinement the speed
+    criterion asks for in leaf 3; region C, also levels 1..1, lies in leaf 3
+    and only touches leaf 2 along x = 160 (no overlap), which refines on its
+    speed.  Without regions: leaves 0 and 1 coarsen, 2 and 3 refine."""
+    h = 0.04
+    mom = [(2, 1, 2.0 * h), (3, 1, 2.0 * h)]
+    assert _tag_lake(oracle_mod, [h] * 4, mom, tag_u_refine=1.0).tolist() == [-1, -1, 1, 1]
+    regions = [(10.0, 10.0, 20.0, 20.0, 2, 3), (200.0, 150.0, 210.0, 170.0, 1, 1), (160.0, 170.0, 170.0, 180.0, 1, 1)]
+    fl = _tag_lake(oracle_mod, [h] * 4, mom, tag_u_refine=1.0, regions=regions)
+    assert fl.tolist() == [1, 0, 1, 0]
+    # a region asking for more than max_level: the level limit wins
+    fl = _tag_lake(oracle_mod, [h] * 4, max_level=1, regions=[(0.0, 0.0, 320.0, 320.0, 3, 3)])
+    assert fl.tolist() == [0, 0, 0, 0]
+
+
+def test_tagging_flow_grades(oracle_mod):
+    """Grades: depth above 0.035 m -> level 2, speed above 0.5 m/s -> level 0;
+    U_r = 0.5 m/s.  Leaf 0 (h 0.04) refines to reach level 2; leaf 1 (h 0.03,
+    u 0.6) coarsens to level 0 although the speed criterion asks for
+    refinement; leaf 2 (h 0.04, u 0.6) takes the larger level and refines;
+    leaf 3 (h 0.03, u 0.3) meets no grade and keeps on the half speed
+    threshold."""
+    grades = [(0, 0.035, 2), (1, 0.5, 0)]
+    fl = _tag_lake(oracle_mod, [0.04, 0.03, 0.04, 0.03], [(1, 1, 0.6 * 0.03), (2, 2, -0.6 * 0.04), (3, 1, 0.3 * 0.03)],
+                   tag_u_refine=0.5, grades=grades)
+    assert fl.tolist() == [1, -1, 1, 0]
+
+
 # -------------------------------------------------------------------- regrid
 def _naive_balance(leaves, refine, lmax):
     """Repeat-until-stable 2:1 face+corner balance on a set of (level, PI, PJ)."""
