@@ -179,6 +179,21 @@ int gf_step_plain(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_s
  * nullable (the flags are kept for gf_regrid). */
 int gf_tag(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
 
+/* Gauges: the time series at control points that Section 5 plots.  Point k
+ * (scenario scen[k], x = xy[2k], y = xy[2k+1], inside its domain) reads the
+ * leaf cell holding it: cell floor((x - x0)/dx), floor((y - y0)/dy) at the
+ * leaf's level (the last cell for a point on the far edge), found again after
+ * every mesh change.  Each accepted step of gf_step or gf_step_plain appends
+ * (t, h, hu, hv, b) of that cell after refluxing, up to `cap` records per
+ * gauge; later records are counted, not kept.  Replaces earlier gauges and
+ * clears their records; n = 0 removes them.  Errors: GF_E_INVALID (n above
+ * 256, a point outside its domain, cap < 1), GF_E_NOMEM/GF_E_HIP. */
+int gf_set_gauges(gf_ctx *ctx, int32_t n, const int32_t *scen, const double *xy, int64_t cap);
+/* Records of gauge g, oldest first: up to cap_out rows of 5 doubles
+ * (t, h, hu, hv, b) into out; *n receives the number of records taken so far
+ * (which may exceed what was kept). */
+int gf_get_gauges(gf_ctx *ctx, int32_t g, double *out, int64_t cap_out, int64_t *n);
+
 /* Apply flags (NULL: those of the last gf_tag): refine, close under 2:1
  * face+corner balance, coarsen complete families whose parent stays
  * balanced; refinement by one level at a time (Section 4: no skipped

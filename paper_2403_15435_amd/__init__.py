@@ -54,7 +54,7 @@ NET_FEATURES = 2304
 
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain",
-           "gf_tag", "gf_regrid", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
+           "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
            "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_split", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
            "gf_net_forward", "gf_net_train_step", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
 
@@ -81,6 +81,8 @@ def load(path: str = LIB_PATH):
     L.gf_destroy.restype = None
     L.gf_set_bathymetry.argtypes = [vp, i32, dp, i64, i64, i32]
     L.gf_set_leaves.argtypes = [vp, i32, C.POINTER(i32), i64]
+    L.gf_set_gauges.argtypes = [vp, i32, C.POINTER(i32), dp, i64]
+    L.gf_get_gauges.argtypes = [vp, i32, dp, i64, C.POINTER(i64)]
     L.gf_get_leaves.argtypes = [vp, i32, C.POINTER(i32), i64, C.POINTER(i64)]
     L.gf_set_patch.argtypes = [vp, i32, i64, i32, dp]
     L.gf_get_patch.argtypes = [vp, i32, i64, i32, dp]
@@ -270,6 +272,23 @@ class Context:
         out = np.zeros(n.value, dtype=np.int8)
         self._chk(self.L.gf_tag(self._p, out.ctypes.data_as(C.POINTER(C.c_int8)), n.value, C.byref(n)))
         return out
+
+    def set_gauges(self, points, cap: int = 4096):
+        """Gauges at points [(scenario, x, y)], up to cap records each."""
+        pts = list(points)
+        sc = np.ascontiguousarray([int(p[0]) for p in pts] or [0], dtype=np.int32)
+        xy = np.ascontiguousarray([(float(p[1]), float(p[2])) for p in pts] or [(0.0, 0.0)], dtype=np.float64)
+        self._chk(self.L.gf_set_gauges(self._p, len(pts), sc.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(xy), cap))
+        self._gauge_cap = cap
+
+    def gauge(self, g: int) -> np.ndarray:
+        """Records of gauge g as rows (t, h, hu, hv, b)."""
+        n = C.c_int64()
+        self._chk(self.L.gf_get_gauges(self._p, g, None, 0, C.byref(n)))
+        k = min(n.value, self._gauge_cap)
+        out = np.zeros((max(k, 1), 5))
+        self._chk(self.L.gf_get_gauges(self._p, g, _dptr(out), k, C.byref(n)))
+        return out[:k]
 
     def regrid(self, flags: Optional[np.ndarray] = None) -> int:
         n = C.c_int64()

@@ -21,6 +21,7 @@ using namespace gf;
 namespace {
 
 constexpr int kMaxHydro = 16;
+constexpr int kMaxGauges = 256;
 
 struct Leaf {
     int32_t level;
@@ -195,6 +196,14 @@ struct gf_ctx {
     int8_t *d_flags = nullptr;
     double *d_mass = nullptr;
     TagRules *d_rules = nullptr;
+    // gauges: points, their cells on the current mesh, device records
+    struct GaugePoint { int32_t scen; double x, y; };
+    std::vector<GaugePoint> gauges;
+    GaugeDev *d_gauges = nullptr;
+    double *d_grec = nullptr;
+    int64_t *d_gcount = nullptr;
+    int64_t grec_cap = 0;
+    bool gauges_on = true;   // off during the tuner's trial steps
     XferTaskH *d_xfer = nullptr;
     int64_t xfer_cap = 0;
     // host mirrors
@@ -554,6 +563,48 @@ bool leaf_desc(const gf_ctx *c, int si, const Scen &s, const Leaf &L, PatchDesc 
 // work list: PatchDesc per leaf (scenario order, leaf order) and reflux tasks
 // in the same order.  Large meshes are described by several host threads,
 // each on a contiguous range of leaves.
+// The leaf cell holding each gauge point: cell (I, J) = floor((p - origin) /
+// spacing) at a level, the last cell for a point on the far edge; the leaf
+// is the one whose patch holds that cell at its own level.
+int map_gauges(gf_ctx *c)
+{
+    if (c->gauges.empty()) return GF_OK;
+    std::vector<GaugeDev> g(c->gauges.size());
+    for (size_t k = 0; k < c->gauges.size(); ++k) {
+        const auto &p = c->gauges[k];
+        const Scen &s = c->sc[(size_t)p.scen];
+        bool found = false;
+        for (int l = s.d.max_level; l >= s.d.min_level && !found; --l) {
+            int64_t I = (int64_t)std::floor((p.x - s.d.x0) / DXl(c, s, l));
+            int64_t J = (int64_t)std::floor((p.y - s.d.y0) / DYl(c, s, l));
+            I = std::min<int64_t>(std::max<int64_t>(I, 0), NI(c, s, l) - 1);
+            J = std::min<int64_t>(std::max<int64_t>(J, 0), NJ(c, s, l) - 1);
+            const int32_t li = s.map.get(key_of(l, I / c->m, J / c->m));
+            if (li < 0) continue;
+            const Leaf &L = s.leaves[(size_t)li];
+            g[k] = GaugeDev{p.scen, L.slot, (int32_t)((J % c->m) * c->m + (I % c->m)), 0};
+            found = true;
+        }
+        if (!found) return fail(c, GF_E_INVALID, "gauge %zu: no leaf holds the point", k);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_gauges, g.data(), sizeof(GaugeDev) * g.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GF_OK;
+}
+
+int launch_gauges(gf_ctx *c)
+{
+    if (c->gauges.empty() || !c->gauges_on) return GF_OK;
+    const int n = (int)c->gauges.size();
+    hipError_t e = c->prec == GF_FP32
+        ? gf_launch_gauge_f32(c->d_gauges, n, c->d_scen, (const float *)c->q[0], (const float *)c->q[1],
+                              (const float *)c->b, c->cap, c->m, c->grec_cap, c->d_grec, c->d_gcount, c->stream)
+        : gf_launch_gauge_f64(c->d_gauges, n, c->d_scen, (const double *)c->q[0], (const double *)c->q[1],
+                              (const double *)c->b, c->cap, c->m, c->grec_cap, c->d_grec, c->d_gcount, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "gauge launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
 int rebuild_work(gf_ctx *c)
 {
     std::vector<std::pair<int, int64_t>> first;   // (scenario, global index of its first leaf)
@@ -623,7 +674,7 @@ int rebuild_work(gf_ctx *c)
         HIPCHK(c, hipMemcpyAsync(c->d_reflux, c->reflux.data(), sizeof(RefluxTask) * c->reflux.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->topo_dirty = false;
-    return GF_OK;
+    return map_gauges(c);
 }
 
 int push_scen(gf_ctx *c)
@@ -757,7 +808,10 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         HIPCHK(c, hipEventRecord(c->ev[evk + 2], c->stream));
         c->prof_launches++;
     }
-    if (mode == 0) return launch_reflux(c);
+    if (mode == 0) {
+        int rc = launch_reflux(c);
+        return rc ? rc : launch_gauges(c);
+    }
     return GF_OK;
 }
 
@@ -892,7 +946,10 @@ int plain_attempt(gf_ctx *c, const std::vector<PlainGroup> &groups, double dt_fi
     }
     int rc = push_scen(c);
     if (rc) return rc;
-    if (mode == 0 && any_accepted) return launch_reflux(c);
+    if (mode == 0 && any_accepted) {
+        rc = launch_reflux(c);
+        return rc ? rc : launch_gauges(c);
+    }
     return GF_OK;
 }
 
@@ -1114,7 +1171,7 @@ void gf_destroy(gf_ctx *c)
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_rules, c->d_mass, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
                   c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats,
-                  c->d_sstage, c->d_sslots};
+                  c->d_sstage, c->d_sslots, c->d_gauges, c->d_grec, c->d_gcount};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -2159,6 +2216,54 @@ void cache_store(const char *path, const std::string &key, int nt, int sched, do
 
 }  // namespace
 
+int gf_set_gauges(gf_ctx *c, int32_t n, const int32_t *scen, const double *xy, int64_t cap)
+{
+    if (!c || n < 0 || n > kMaxGauges || (n > 0 && (!scen || !xy || cap < 1))) return GF_E_INVALID;
+    std::vector<gf_ctx::GaugePoint> pts((size_t)n);
+    for (int k = 0; k < n; ++k) {
+        if (scen[k] < 0 || scen[k] >= (int)c->sc.size()) return fail(c, GF_E_INVALID, "gauge %d: no scenario %d", k, scen[k]);
+        const gf_scenario_desc &d = c->sc[(size_t)scen[k]].d;
+        const double x = xy[2 * k], y = xy[2 * k + 1];
+        if (!(x >= d.x0 && x <= d.x1 && y >= d.y0 && y <= d.y1))
+            return fail(c, GF_E_INVALID, "gauge %d: point outside its domain", k);
+        pts[(size_t)k] = {scen[k], x, y};
+    }
+    if (c->d_gauges) { (void)hipFree(c->d_gauges); c->d_gauges = nullptr; }
+    if (c->d_grec) { (void)hipFree(c->d_grec); c->d_grec = nullptr; }
+    if (c->d_gcount) { (void)hipFree(c->d_gcount); c->d_gcount = nullptr; }
+    c->gauges.clear();
+    c->grec_cap = 0;
+    if (n == 0) return GF_OK;
+    HIPCHK(c, hipMalloc((void **)&c->d_gauges, sizeof(GaugeDev) * (size_t)n));
+    HIPCHK(c, hipMalloc((void **)&c->d_grec, sizeof(double) * 5 * (size_t)n * (size_t)cap));
+    HIPCHK(c, hipMalloc((void **)&c->d_gcount, sizeof(int64_t) * (size_t)n));
+    HIPCHK(c, hipMemsetAsync(c->d_gcount, 0, sizeof(int64_t) * (size_t)n, c->stream));
+    c->gauges = pts;
+    c->grec_cap = cap;
+    bool ready = true;
+    for (auto &s : c->sc) ready = ready && scen_ready(s);
+    if (!ready) return GF_OK;   // mapped when the mesh is built
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    return map_gauges(c);
+}
+
+int gf_get_gauges(gf_ctx *c, int32_t g, double *out, int64_t cap_out, int64_t *n)
+{
+    if (!c || g < 0 || g >= (int)c->gauges.size() || cap_out < 0 || (cap_out > 0 && !out)) return GF_E_INVALID;
+    int64_t cnt = 0;
+    HIPCHK(c, hipMemcpyAsync(&cnt, c->d_gcount + g, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (n) *n = cnt;
+    const int64_t k = std::min(std::min(cnt, c->grec_cap), cap_out);
+    if (k > 0) {
+        HIPCHK(c, hipMemcpyAsync(out, c->d_grec + (size_t)g * (size_t)c->grec_cap * 5, sizeof(double) * 5 * (size_t)k,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return GF_OK;
+}
+
 int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threads_out, int32_t *sched_out,
                 double *us_per_step_out)
 {
@@ -2206,6 +2311,7 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
     const bool flags_dirty0 = c->flags_dirty;
     const int nt0 = c->step_threads, sched0 = c->sched_wg;
     const bool prof0 = c->prof;
+    c->gauges_on = false;
     hipError_t e = copy_all(true);
     static const int cand32[] = {256, 512, 1024}, cand16[] = {64, 128, 256};
     const int *cand = c->m == 16 ? cand16 : cand32;
@@ -2238,6 +2344,7 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
         }
     c->prof = prof0;
     c->prof_launches = 0;
+    c->gauges_on = true;
     // the trials may have rewritten face records of patches the snapshot
     // holds as stable: every patch goes back to full dry updates
     if (e == hipSuccess) e = hipMemsetAsync(c->d_dstab, 0, (size_t)c->cap, c->stream);

@@ -75,6 +75,11 @@ struct TagRules {
     int32_t grade_lev[kMaxGrades];
 };
 
+// A gauge: the cell of the current mesh that holds the point.
+struct GaugeDev {
+    int32_t scen, slot, cell, pad;
+};
+
 template <typename R>
 struct StepArgs {
     const PatchDesc *desc;
@@ -133,6 +138,9 @@ struct RefluxArgsBase {
                                    const R *q0, const R *q1, const R *b, int64_t cap,              \
                                    const gf::TagRules *rules, double tau64, int8_t *flags, int m,  \
                                    hipStream_t s);                                                 \
+    hipError_t gf_launch_gauge_##SFX(const gf::GaugeDev *g, int n, const gf::ScenDev *scen,        \
+                                     const R *q0, const R *q1, const R *b, int64_t cap, int m,       \
+                                     int64_t rec_cap, double *rec, int64_t *count, hipStream_t s);   \
     hipError_t gf_launch_mass_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,        \
                                     const R *q0, const R *q1, int64_t cap, double *out, int m,     \
                                     hipStream_t s);                                                 \

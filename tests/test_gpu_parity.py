@@ -604,6 +604,76 @@ def test_refinement_rules_tag_regrid_bit_exact(orc, prec):
     assert all(v > 0 for v in moved.values()), moved
 
 
+def _gauge_cell(sc, leaves, st, x, y):
+    """(h, hu, hv, b) of the leaf cell holding (x, y): cell floor((p - origin)
+    / spacing) at the leaf's level, the last cell on the far edge."""
+    for l in range(sc.max_level, sc.min_level - 1, -1):
+        n = sc.mi * sc.m << l
+        I = min(max(int(np.floor((x - sc.x0) / sc.dx(l))), 0), n - 1)
+        J = min(max(int(np.floor((y - sc.y0) / sc.dy(l))), 0), (sc.mj * sc.m << l) - 1)
+        PI, PJ = I // sc.m, J // sc.m
+        for k, (t, lv, ix, iy) in enumerate(leaves):
+            ti, tj = t % sc.mi, t // sc.mi
+            if lv == l and ti * (1 << l) + ix == PI and tj * (1 << l) + iy == PJ:
+                return tuple(st[k, :, J % sc.m, I % sc.m])
+    raise AssertionError("no leaf holds the point")
+
+
+def test_gauges_record_the_oracle_cells_through_regrids(orc):
+    """Gauges at six points (a patch corner, the domain's two extreme corners,
+    points in coarse and fine leaves and at the front): every accepted step's
+    record equals the oracle's cell after that step, bit for bit, over three
+    regrids, on the fused and on the plain path."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=4, radius=400.0)
+    sc.min_level, sc.max_level = 1, 4
+    pts = [(0, 1000.0, 1000.0), (0, 1234.5, 987.6), (0, 600.0, 1400.0), (0, 2000.0, 2000.0), (0, 0.0, 0.0),
+           (0, 1410.0, 1000.0)]
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    a = gf.Context([sc], precision=gf.GF_FP64, max_patches=1024)
+    b = gf.Context([sc], precision=gf.GF_FP64, max_patches=1024)
+    for ctx in (a, b):
+        gpu_init_like(ctx, o, "f64")
+        ctx.set_gauges(pts, cap=64)
+    want = [[] for _ in pts]
+    for cycle in range(3):
+        dts = []
+        for k in range(6):
+            _, d = o.advance(1, return_dt=True)
+            dts += list(d)
+            lv, st = o.leaves(), o.state()
+            for gi, (_, x, y) in enumerate(pts):
+                want[gi].append((o.t,) + _gauge_cell(sc, lv, st, x, y))
+        a.step(len(dts), dts)
+        b.step(len(dts), dts, plain=True)
+        fo = o.tag()
+        assert np.array_equal(a.tag(), fo) and np.array_equal(b.tag(), fo)
+        o.regrid(fo)
+        a.regrid(None)
+        b.regrid(None)
+    assert len(set(o.leaves()[:, 1].tolist())) >= 2
+    for gi in range(len(pts)):
+        w = np.array(want[gi])
+        assert w.shape == (18, 5)
+        assert np.array_equal(a.gauge(gi), w), gi
+        assert np.array_equal(b.gauge(gi), w), gi
+    print("gauge 5 depth series:", " ".join(f"{v:.3f}" for v in np.array(want[5])[:, 1]), flush=True)
+
+
+def test_gauge_arguments_are_checked():
+    sc = inputs.reservoir_fractal(level=1, m=16, L=2000.0, seed=4, radius=400.0)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=16)
+    ctx.set_initial(0)
+    with pytest.raises(gf.GFError):
+        ctx.set_gauges([(0, 2000.5, 10.0)])
+    with pytest.raises(gf.GFError):
+        ctx.set_gauges([(1, 10.0, 10.0)])
+    ctx.set_gauges([(0, 10.0, 10.0)], cap=2)
+    ctx.step(3)
+    assert ctx.gauge(0).shape == (2, 5)
+    ctx.set_gauges([])
+
+
 # ------------------------------------------------------------ invariants
 @pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
 def test_lake_at_rest_bit_exact(orc, prec):
