@@ -157,6 +157,76 @@ def valley_amr(steps, warmup, regrid_every=4, t0=4000.0):
     return out
 
 
+def flood_speed_amr(steps, warmup, regrid_every=4, t_spin=1800.0):
+    """The floodplain workload (flat 1 km x 2 km, 20 m inlet, trapezoid
+    hydrograph to 20 m^3/s, n = 0.03, dry start) on AMR levels 0-3 of 32 x 32
+    patches (5.2 m to 0.65 m cells), depth-tagged, the inlet held at the
+    finest level: spun up on the FP32 path to t_spin, then timed on the fused
+    FP32, fused FP64 and plain FP64 paths from that mesh and state (widened),
+    tag and regrid every `regrid_every` steps."""
+    import paper_2403_15435_amd as gf
+    from paper_2403_15435_amd import inputs
+    sc = inputs.flood_speed()
+    cap = 8192
+    base = gf.Context([sc], precision=gf.GF_FP32, max_patches=cap)
+    base.set_initial(0)
+    spin = 0
+    while base.time(0)[0] < t_spin:
+        base.tag()
+        base.regrid(None)
+        base.step(regrid_every)
+        spin += regrid_every
+    base.tag()
+    base.regrid(None)
+    leaves0, state0, t0 = base.leaves(0), base.state(0), base.time(0)[0]
+    base.close()
+    print(f"[bench] floodplain at t = {t0:.0f} s after {spin} steps: {leaves0.shape[0]} leaves, levels "
+          f"{np.bincount(leaves0[:, 1]).tolist()}", file=sys.stderr, flush=True)
+    out = {"workload": "floodplain: flat 1000 m x 2000 m, inflow over 990-1010 m of x = 0, trapezoid hydrograph "
+                       "0 -> 20 m^3/s (60/180/60 min), n = 0.03, walls, dry start; 6x12 trees, levels 0-3 of 32x32 "
+                       "patches (5.2 m to 0.65 m), depth tagging (0.05 m), inlet region at level 3, regrid every 4 "
+                       "steps; timed from t = 30 min",
+           "t_start_s": t0, "leaves_start": int(leaves0.shape[0]), "steps": steps, "regrid_every": regrid_every}
+    for name, prec, plain in (("fp32_fused", gf.GF_FP32, False), ("fp64_fused", gf.GF_FP64, False),
+                              ("fp64_plain", gf.GF_FP64, True)):
+        ctx = gf.Context([sc], precision=prec, max_patches=cap)
+        ctx.set_leaves(0, leaves0)
+        ctx.set_state(0, state0[:, :3])
+        ctx.set_time(0, t0)
+        if not plain:
+            ctx.autotune(steps=3)
+
+        def cycle():
+            _sync()
+            a = time.perf_counter()
+            st = ctx.step(regrid_every, plain=plain)
+            _sync()
+            b = time.perf_counter()
+            ctx.tag()
+            ctx.regrid(None)
+            return st, b - a, time.perf_counter() - b
+        for _ in range(max(warmup // regrid_every, 1)):
+            cycle()
+        m0 = ctx.mass(0)
+        t_step = t_regrid = 0.0
+        cells = 0
+        for _ in range(steps // regrid_every):
+            st, ts, tr = cycle()
+            t_step += ts
+            t_regrid += tr
+            cells += int(st.cell_updates)
+        M = ctx.mass(0)
+        out[name] = {"step_cell_updates_per_s": cells / t_step,
+                     "end_to_end_cell_updates_per_s": cells / (t_step + t_regrid), "step_s": t_step,
+                     "tag_regrid_s": t_regrid, "leaves_end": int(ctx.leaves(0).shape[0]),
+                     "budget_residual_rel": float(((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) / M[0])}
+        print(f"[bench] floodplain {name}: {out[name]}", file=sys.stderr, flush=True)
+        ctx.close()
+    out["speedup_fp32_fused_over_fp64_plain"] = (out["fp32_fused"]["step_cell_updates_per_s"]
+                                                 / out["fp64_plain"]["step_cell_updates_per_s"])
+    return out
+
+
 def ensemble(steps, warmup, n_scen=256):
     """The batched workload: 256 independent dam breaks on seeded fractal
     terrain (grids of 64^2 to 512^2 cells as 32 x 32 patches, n ~ U[0.02,
@@ -378,7 +448,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=0, help="steps of the plain FP64 run (0: the same as --steps)")
     ap.add_argument("--amr-steps", type=int, default=400, help="steps of each AMR valley run (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=200, help="steps of each ensemble run (0: skip)")
-    ap.add_argument("--only", choices=["valley", "ensemble", "learned"], default=None,
+    ap.add_argument("--flood-steps", type=int, default=400, help="steps of each floodplain AMR run (0: skip)")
+    ap.add_argument("--only", choices=["valley", "ensemble", "learned", "flood"], default=None,
                     help="run only this extra workload and print its section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM byte counters)")
@@ -394,6 +465,9 @@ def main():
         return
     if args.only == "ensemble":
         print(json.dumps(ensemble(args.ensemble_steps, 10)))
+        return
+    if args.only == "flood":
+        print(json.dumps(flood_speed_amr(args.flood_steps, 40)))
         return
     if args.only == "learned":
         print(json.dumps(learned_tagger()))
@@ -444,6 +518,7 @@ def main():
     achieved = BYTES_PER_UPDATE["f32"] * cells_per_launch / avg_launch_s / 1e9
     amr = guarded(valley_amr, args.amr_steps, 40) if args.amr_steps > 0 else None
     ens = guarded(ensemble, args.ensemble_steps, 10) if args.ensemble_steps > 0 else None
+    flood = guarded(flood_speed_amr, args.flood_steps, 40) if args.flood_steps > 0 else None
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sc)
@@ -481,6 +556,7 @@ def main():
         "all_wet": wet,
         "amr_valley": amr,
         "ensemble": ens,
+        "amr_floodplain": flood,
     }
     print(json.dumps(line))
 

@@ -370,6 +370,32 @@ def v_valley(level_max: int = 6, m: int = 32, seed: int = 3, min_level: int = 0,
     return sc
 
 
+def flood_speed(level_max: int = 3, m: int = 32, min_level: int = 0, mi: int = 6, mj: int = 12,
+                q_peak: float = 20.0, manning_n: float = 0.03, tag_h: float = 0.05) -> Scenario:
+    """Speed of flood propagation over an extended floodplain: flat bed at 0 m,
+    x in [0, 1000] m, y in [0, 2000] m, dry start; inflow over 990 <= y <= 1010
+    at x = 0 following a trapezoid hydrograph 0 -> q_peak m^3/s (60 min rise,
+    180 min plateau, 60 min fall), walls elsewhere; n = manning_n; run to 6 h.
+    Level-0 cells are 1000 / (mi m) m wide (5.2 m for 6 x 12 trees of 32^2:
+    a 5 m grid has 200 cells across, which no power-of-two patch divides).
+    Tagging: depth above tag_h, and a flood-source region over the inlet held
+    at the finest level."""
+    lx, ly = 1000.0, 2000.0
+    sc = Scenario(name="flood_speed", x0=0.0, y0=0.0, x1=lx, y1=ly, mi=mi, mj=mj, m=m,
+                  min_level=min_level, max_level=level_max, manning_n=manning_n,
+                  bc=(BC_INFLOW, BC_WALL, BC_WALL, BC_WALL), inflow_side=0, inflow_lo=990.0, inflow_hi=1010.0,
+                  hydro=trapezoid_hydrograph(q_peak, 3600.0, 10800.0, 3600.0), tag_h_refine=tag_h,
+                  t_end=6 * 3600.0, init_level=min_level,
+                  regions=[(0.0, 980.0, 20.0, 1020.0, level_max, level_max)])
+    sc.dem = np.zeros((mj * m + 1, mi * m + 1))
+    sc.dem_level = 0
+
+    def eta(X, Y, b):
+        return b - 1.0
+    sc.eta_fn = eta
+    return sc
+
+
 def ensemble_dambreaks(n_scen: int = 256, master_seed: int = 4000, m: int = 32,
                        dx: float = 10.0, sizes=(64, 128, 256, 512)) -> List[Scenario]:
     """Independent dam-break scenarios: N_k ~ U{sizes}, L = dx N_k, fractal

@@ -674,6 +674,42 @@ def test_gauge_arguments_are_checked():
     ctx.set_gauges([])
 
 
+def test_flood_speed_amr_against_oracle(orc):
+    """The floodplain case on AMR levels 0..2 (10.4 m to 2.6 m cells), the
+    inlet held at the finest level by its flood-source region, from the dry
+    start: 15 cycles of tag, regrid and 4 steps.  FP64: flags, leaves and
+    state bit-identical to the oracle throughout.  FP32 on its own mesh, with
+    the same step lengths: its volume budget closes and it takes in the FP64
+    inflow volume within 1e-4."""
+    sc = inputs.flood_speed(level_max=2, m=16, mi=6, mj=12)
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    a = gf.Context([sc], precision=gf.GF_FP64, max_patches=4096)
+    f = gf.Context([sc], precision=gf.GF_FP32, max_patches=4096)
+    gpu_init_like(a, o, "f64")
+    gpu_init_like(f, o, "f32")
+    for cycle in range(15):
+        fo = o.tag()
+        assert np.array_equal(a.tag(), fo), cycle
+        assert o.regrid(fo) == a.regrid(None)
+        f.tag()
+        f.regrid(None)
+        assert np.array_equal(o.leaves(), a.leaves(0)), cycle
+        _, dts = o.advance(4, return_dt=True)
+        a.step(len(dts), dts)
+        f.step(len(dts), dts)
+        assert np.array_equal(a.state(0)[:, :3], o.state()[:, :3]), cycle
+    lv = o.leaves()
+    print(f"floodplain AMR at t = {o.t:.1f} s: {lv.shape[0]} leaves, levels {np.bincount(lv[:, 1]).tolist()}", flush=True)
+    assert (lv[:, 1] == 2).any()
+    M, cl, bd = a.mass(0)
+    assert bd > 0.0 and abs(M - cl - bd) <= 1e-12 * M
+    M32, cl32, bd32 = f.mass(0)
+    assert abs(M32 - cl32 - bd32) <= 1e-6 * M32
+    print(f"inflow volume: fp32 {bd32:.6e}, fp64 {bd:.6e} m^3", flush=True)
+    assert abs(bd32 - bd) <= 1e-4 * bd
+
+
 # ------------------------------------------------------------ invariants
 @pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
 def test_lake_at_rest_bit_exact(orc, prec):

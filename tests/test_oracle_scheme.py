@@ -489,3 +489,40 @@ def test_smooth_hump_converges_at_second_order(oracle_mod):
     orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
     assert min(orders) >= 1.8, (errs, orders)
     assert errs[-1] <= 2e-6, errs
+
+
+# ------------------------------------------- flood over an extended floodplain
+def test_flood_speed_budget_and_symmetries(oracle_mod):
+    """The floodplain case on a uniform 10.4 m grid (96 x 192 cells) to t = 30
+    min: the volume budget closes to round-off; the inflow volume is within 2%
+    of the hydrograph's integral times the length of the ghost cells whose
+    centres lie in the inlet segment (two cells of 10.4 m); the solution is
+    mirror-symmetric about the inlet's axis y = 1000 m to round-off; and the
+    flood is nearly radial, its front (h > 1 mm) at the same distance from the
+    inlet within 3% along five rays from 0 to 90 degrees."""
+    sc = inputs.flood_speed(level_max=0, m=16, mi=6, mj=12)
+    sc.regions = None
+    sc.t_end = 1800.0
+    o = oracle_mod.Oracle(sc)
+    init_oracle(o, sc)
+    o.advance(100000)
+    assert o.t == 1800.0
+    H = assemble(sc, o.leaves(), o.state(), 0)
+    HV = assemble(sc, o.leaves(), o.state(), 2)
+    M, cl, bd = o.mass()
+    assert abs(M - cl - bd) <= 1e-13 * M
+    dx = sc.dx(0)
+    ncov = sum(1 for J in range(H.shape[0]) if 990.0 <= (J + 0.5) * dx <= 1010.0)
+    assert ncov == 2
+    v_in = 20.0 * 1800.0 ** 2 / (2 * 3600.0) * (ncov * dx / 20.0)
+    assert abs(bd / v_in - 1.0) <= 0.02
+    assert np.abs(H - H[::-1]).max() <= 1e-10 * H.max()
+    assert np.abs(HV + HV[::-1]).max() <= 1e-10 * np.abs(HV).max()
+    yc = (np.arange(H.shape[0]) + 0.5) * dx
+    xc = (np.arange(H.shape[1]) + 0.5) * dx
+    X, Y = np.meshgrid(xc, yc)
+    R = np.hypot(X, Y - 1000.0)
+    ang = np.degrees(np.arctan2(Y - 1000.0, X))
+    fronts = [R[(H > 1e-3) & (np.abs(ang - a) < 3.0)].max() for a in (0.0, 22.5, 45.0, 67.5, 90.0)]
+    assert max(fronts) <= 1.03 * min(fronts)
+    assert 150.0 < min(fronts) < 400.0
