@@ -58,6 +58,7 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, C.c_double]
         L.orc_step.restype = C.c_double
         L.orc_advance.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.orc_advance_lts.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
         L.orc_set_bathy_f32.argtypes = [C.c_void_p, C.c_int]
         L.orc_mass.argtypes = [C.c_void_p, _dp]
         L.orc_tag.argtypes = [C.c_void_p, C.POINTER(C.c_byte)]
@@ -197,17 +198,19 @@ class Oracle:
         """One step of length dt; returns max|s|/dx.  Does not advance the clock."""
         return lib().orc_step(self._p, dt)
 
-    def advance(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None, return_dt: bool = False):
+    def advance(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None, return_dt: bool = False,
+                lts: bool = False):
         """Advance with adaptive or fixed steps; returns the Courant numbers of the
-        accepted steps (and their lengths if return_dt)."""
+        accepted steps (and their lengths if return_dt).  lts: each step is a
+        macro step of local time stepping (dt that of the coarsest level)."""
         nu = np.zeros(max(nsteps, 1))
         dts = np.zeros(max(nsteps, 1))
         s0 = self.steps
         if dt_fixed is not None:
             d = np.ascontiguousarray(dt_fixed, dtype=np.float64)
-            rc = lib().orc_advance(self._p, nsteps, _d(d), _d(nu), _d(dts))
+            rc = (lib().orc_advance_lts if lts else lib().orc_advance)(self._p, nsteps, _d(d), _d(nu), _d(dts))
         else:
-            rc = lib().orc_advance(self._p, nsteps, None, _d(nu), _d(dts))
+            rc = (lib().orc_advance_lts if lts else lib().orc_advance)(self._p, nsteps, None, _d(nu), _d(dts))
         if rc != 0:
             raise RuntimeError(f"oracle advance failed ({rc})")
         k = self.steps - s0

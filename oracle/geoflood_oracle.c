@@ -664,12 +664,16 @@ static double minmod(double a, double b)
  * stencil to C keeps each ghost value a function of its position alone, so
  * leaves that share a ghost position (a face ghost of one, a corner ghost of
  * another) see identical values and same-level faces stay conservative. */
-static int coarse_value(const orc_sim *s, const leaf_t *C, long Ic, long Jc, double v[4])
+static int coarse_value(const orc_sim *s, const leaf_t *C, double *const *Cprev, long Ic, long Jc, double v[4])
 {
     int m = s->m, f;
     long ci = Ic - C->PI * m, cj = Jc - C->PJ * m;
     if (ci >= 0 && ci < m && cj >= 0 && cj < m) {
-        for (f = 0; f < 3; ++f) v[f] = C->q[f][G(s, (int)ci, (int)cj)];
+        /* with Cprev (local time stepping, reading R40): the coarse state
+           halfway through its step, the mean of its states before and after */
+        for (f = 0; f < 3; ++f)
+            v[f] = Cprev ? 0.5 * (Cprev[f][G(s, (int)ci, (int)cj)] + C->q[f][G(s, (int)ci, (int)cj)])
+                         : C->q[f][G(s, (int)ci, (int)cj)];
         v[3] = C->b[G(s, (int)ci, (int)cj)];
         return 1;
     }
@@ -680,7 +684,7 @@ static int coarse_value(const orc_sim *s, const leaf_t *C, long Ic, long Jc, dou
  * minmod slopes of eta = h + b (differences formed as dh + db) when the
  * parent and its available neighbours are wet, constant free surface when
  * only the parent is wet, dry otherwise; momenta minmod-linear. */
-static void interp_coarse_to_fine(const orc_sim *s, const leaf_t *C, long I, long J,
+static void interp_coarse_to_fine(const orc_sim *s, const leaf_t *C, double *const *Cprev, long I, long J,
                                   double bf, double out[3])
 {
     long Ic = I >> 1, Jc = J >> 1;
@@ -688,11 +692,11 @@ static void interp_coarse_to_fine(const orc_sim *s, const leaf_t *C, long I, lon
     int hasE, hasW, hasN, hasS, allwet, f;
     double sx = (I & 1) ? 1.0 : -1.0, sy = (J & 1) ? 1.0 : -1.0;
     double sigx, sigy, h;
-    coarse_value(s, C, Ic, Jc, P);
-    hasE = coarse_value(s, C, Ic + 1, Jc, E);
-    hasW = coarse_value(s, C, Ic - 1, Jc, W);
-    hasN = coarse_value(s, C, Ic, Jc + 1, N);
-    hasS = coarse_value(s, C, Ic, Jc - 1, S);
+    coarse_value(s, C, Cprev, Ic, Jc, P);
+    hasE = coarse_value(s, C, Cprev, Ic + 1, Jc, E);
+    hasW = coarse_value(s, C, Cprev, Ic - 1, Jc, W);
+    hasN = coarse_value(s, C, Cprev, Ic, Jc + 1, N);
+    hasS = coarse_value(s, C, Cprev, Ic, Jc - 1, S);
     allwet = wet(s, P[0]) && (!hasE || wet(s, E[0])) && (!hasW || wet(s, W[0])) &&
              (!hasN || wet(s, N[0])) && (!hasS || wet(s, S[0]));
     if (wet(s, P[0]) && allwet) {
@@ -719,12 +723,16 @@ static void interp_coarse_to_fine(const orc_sim *s, const leaf_t *C, long I, lon
  * only interior cells of other leaves (and of the leaf itself), so the
  * same-level, fine-to-coarse and coarse-to-fine phases are independent; the
  * physical boundary rules run last. */
-void orc_fill_ghosts_at(orc_sim *s, double t)
+/* act (nullable): the leaves to fill; half (nullable): per level, whether a
+   coarser source is read halfway through its step from prev (the sources'
+   states before their last update). */
+static void fill_ghosts_sel(orc_sim *s, double t, const char *act, const char *half, double ***prev)
 {
     int m = s->m, k, i, j, f;
     for (k = 0; k < s->n_leaves; ++k) {
         leaf_t *L = &s->leaves[k];
         long ni = NI(s, L->level), nj = NJ(s, L->level);
+        if (act && !act[k]) continue;
         for (j = -2; j < m + 2; ++j)
             for (i = -2; i < m + 2; ++i) {
                 long I = L->PI * m + i, J = L->PJ * m + j;
@@ -747,7 +755,7 @@ void orc_fill_ghosts_at(orc_sim *s, double t)
                     }
                 } else {
                     double o[3];
-                    interp_coarse_to_fine(s, S, I, J, L->b[G(s, i, j)], o);
+                    interp_coarse_to_fine(s, S, (half && half[L->level]) ? prev[src] : NULL, I, J, L->b[G(s, i, j)], o);
                     for (f = 0; f < 3; ++f) L->q[f][G(s, i, j)] = o[f];
                 }
             }
@@ -755,6 +763,8 @@ void orc_fill_ghosts_at(orc_sim *s, double t)
         inflow_ghosts(s, L, t);
     }
 }
+
+void orc_fill_ghosts_at(orc_sim *s, double t) { fill_ghosts_sel(s, t, NULL, NULL, NULL); }
 
 void orc_fill_ghosts(orc_sim *s) { orc_fill_ghosts_at(s, s->t); }
 
@@ -1008,7 +1018,7 @@ static void correction_flux(const orc_sim *s, const edge_t *E, int e, int r, dou
 /* Advance every leaf by dt (ghosts must be filled).  Stores the new interior
  * into the leaves, the reflux gains into leaf->gain, the boundary mass flux
  * into s->bnd_mass, and returns max over edges of |s|/dx. */
-static double update_all(orc_sim *s, double dt)
+static double update_all(orc_sim *s, double dt, const char *act)
 {
     int m = s->m, k, ne = m + 3;
     double smax_all = 0.0;
@@ -1037,6 +1047,8 @@ static double update_all(orc_sim *s, double dt)
         double sx, sy, smax;
         int i, j, e, r, f, c;
         long ni = NI(s, L->level), nj = NJ(s, L->level);
+        newq[3 * k] = NULL;
+        if (act && !act[k]) continue;
         sx = sweep_solve(s, L, 0, EX);
         sy = sweep_solve(s, L, 1, EY);
         smax = sx / dx > sy / dy ? sx / dx : sy / dy;
@@ -1179,6 +1191,7 @@ static double update_all(orc_sim *s, double dt)
     for (k = 0; k < s->n_leaves; ++k) {
         leaf_t *L = &s->leaves[k];
         int i, j, f;
+        if (!newq[3 * k]) continue;
         for (f = 0; f < 3; ++f) {
             for (j = 0; j < m; ++j)
                 for (i = 0; i < m; ++i) L->q[f][G(s, i, j)] = newq[3 * k + f][j * m + i];
@@ -1239,11 +1252,14 @@ static void clamp_leaf(orc_sim *s, leaf_t *L)
 /* terms and made rough-bed AMR runs unstable.                               */
 /* ------------------------------------------------------------------------ */
 
-static void reflux_all(orc_sim *s)
+/* lev (nullable): only coarse leaves of the levels marked; gacc (nullable):
+   the fine leaves' records summed over their substeps, in place of gainF */
+static void reflux_sel(orc_sim *s, const char *lev, double *const *gacc)
 {
     int m = s->m, k, f, kk, q;
     for (k = 0; k < s->n_leaves; ++k) {
         leaf_t *C = &s->leaves[k];
+        if (lev && !lev[C->level]) continue;
         long ni = NI(s, C->level), nj = NJ(s, C->level);
         double area = DX(s, C->level) * DY(s, C->level);
         int touched = 0;
@@ -1272,7 +1288,7 @@ static void reflux_all(orc_sim *s)
                     if (fsrc < 0 || r2 != 0) { fprintf(stderr, "oracle: reflux lookup\n"); abort(); }
                     F = &s->leaves[fsrc];
                     fk = (f < 2) ? (int)(FJ - F->PJ * m) : (int)(FI - F->PI * m);
-                    for (q = 0; q < 3; ++q) gf[q] += F->gainF[((f ^ 1) * m + fk) * 3 + q];
+                    for (q = 0; q < 3; ++q) gf[q] += (gacc ? gacc[fsrc] : F->gainF)[((f ^ 1) * m + fk) * 3 + q];
                 }
                 (void)src;
                 if (f == 0) { ci = 0; cj = kk; }
@@ -1299,6 +1315,8 @@ static void reflux_all(orc_sim *s)
         if (touched) clamp_leaf(s, C);
     }
 }
+
+static void reflux_all(orc_sim *s) { reflux_sel(s, NULL, NULL); }
 
 /* ------------------------------------------------------------------------ */
 /* time stepping (reading R9, R19)                                           */
@@ -1330,7 +1348,7 @@ double orc_step(orc_sim *s, double dt)
     int k;
     double smax;
     orc_fill_ghosts_at(s, s->t);
-    smax = update_all(s, dt);
+    smax = update_all(s, dt, NULL);
     for (k = 0; k < s->n_leaves; ++k) {
         friction_leaf(s, &s->leaves[k], dt);
         clamp_leaf(s, &s->leaves[k]);
@@ -1384,6 +1402,141 @@ int orc_advance(orc_sim *s, int nsteps, const double *dt_fixed, double *nu_out, 
     }
     free(save);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* local time stepping (reading R40)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* One macro step of length dt at the coarsest level L0 present; level l takes
+ * 2^(l - L0) substeps of dt / 2^(l - L0).  The step is cut into K = 2^(L1 -
+ * L0) ticks of the finest substep; level l starts a substep at tick k when
+ * 2^(L1 - l) divides k, at time t + k (dt / K).  All ghosts of a tick are
+ * filled before any of its updates: same-level and finer sources at their
+ * current state (the same time), a coarser source at its current state when
+ * it starts its own step at this tick too, else halfway through its step
+ * (the mean of its states before and after).  Fine-side face records are
+ * summed over the two substeps; a coarse level is refluxed when its step
+ * ends.  Returns the largest Courant number dt_l max|s|/dx of the updates. */
+static double lts_macro(orc_sim *s, double dt, int L0, int L1, char *act, double ***prev, double **gacc)
+{
+    int m = s->m, k, n, l, f, K = 1 << (L1 - L0);
+    size_t cells = (size_t)(m + 4) * (m + 4);
+    double nu = 0.0;
+    char half[32], done[32];
+    for (n = 0; n < K; ++n) {
+        const double tn = s->t + (double)n * (dt / (double)K);
+        for (l = 0; l < 32; ++l) { half[l] = 0; done[l] = 0; }
+        for (l = L0; l <= L1; ++l) {
+            const int stride = 1 << (L1 - l);
+            half[l] = (l > L0 && (n % (2 * stride)) != 0);
+            done[l] = ((n + 1) % stride) == 0;
+        }
+        for (k = 0; k < s->n_leaves; ++k) act[k] = (n % (1 << (L1 - s->leaves[k].level))) == 0;
+        fill_ghosts_sel(s, tn, act, half, prev);
+        for (k = 0; k < s->n_leaves; ++k)
+            if (act[k])
+                for (f = 0; f < 3; ++f) memcpy(prev[k][f], s->leaves[k].q[f], sizeof(double) * cells);
+        for (l = L0; l <= L1; ++l) {
+            const double dtl = dt / (double)(1 << (l - L0));
+            char *al = (char *)malloc((size_t)s->n_leaves);
+            int any = 0;
+            double sm;
+            for (k = 0; k < s->n_leaves; ++k) { al[k] = act[k] && s->leaves[k].level == l; any |= al[k]; }
+            if (!any) { free(al); continue; }
+            sm = update_all(s, dtl, al);
+            if (dtl * sm > nu) nu = dtl * sm;
+            for (k = 0; k < s->n_leaves; ++k) {
+                if (!al[k]) continue;
+                friction_leaf(s, &s->leaves[k], dtl);
+                clamp_leaf(s, &s->leaves[k]);
+                if (!half[l]) memcpy(gacc[k], s->leaves[k].gainF, sizeof(double) * 12 * (size_t)m);
+                else
+                    for (f = 0; f < 12 * m; ++f) gacc[k][f] = gacc[k][f] + s->leaves[k].gainF[f];
+            }
+            free(al);
+        }
+        reflux_sel(s, done, gacc);
+    }
+    return nu;
+}
+
+/* Largest Courant number per unit macro step: max over leaves of
+ * max|s|/dx / 2^(l - L0). */
+static double lts_speed(orc_sim *s, int L0)
+{
+    int m = s->m, k, ne = m + 3;
+    double smax = 0.0;
+    edge_t *E = (edge_t *)malloc(sizeof(edge_t) * (size_t)(m + 2) * ne);
+    orc_fill_ghosts(s);
+    for (k = 0; k < s->n_leaves; ++k) {
+        leaf_t *L = &s->leaves[k];
+        double a = sweep_solve(s, L, 0, E) / DX(s, L->level);
+        double b = sweep_solve(s, L, 1, E) / DY(s, L->level);
+        double v = (a > b ? a : b) / (double)(1 << (L->level - L0));
+        if (v > smax) smax = v;
+    }
+    free(E);
+    return smax;
+}
+
+/* As orc_advance, with each accepted step a macro step of local time
+ * stepping: dt is the coarsest level's step, and the Courant number is the
+ * largest over every level's substeps. */
+int orc_advance_lts(orc_sim *s, int nsteps, const double *dt_fixed, double *nu_out, double *dt_out)
+{
+    int m = s->m, n, k, f, L0 = 99, L1 = -1;
+    size_t cells = (size_t)(m + 4) * (m + 4);
+    double *save = (double *)malloc(sizeof(double) * cells * 3 * (size_t)s->n_leaves);
+    char *act = (char *)malloc((size_t)s->n_leaves + 1);
+    double ***prev = (double ***)malloc(sizeof(double **) * (size_t)s->n_leaves + 1);
+    double **gacc = (double **)malloc(sizeof(double *) * (size_t)s->n_leaves + 1);
+    for (k = 0; k < s->n_leaves; ++k) {
+        if (s->leaves[k].level < L0) L0 = s->leaves[k].level;
+        if (s->leaves[k].level > L1) L1 = s->leaves[k].level;
+        prev[k] = (double **)malloc(sizeof(double *) * 3);
+        for (f = 0; f < 3; ++f) prev[k][f] = (double *)calloc(cells, sizeof(double));
+        gacc[k] = (double *)calloc((size_t)(12 * m), sizeof(double));
+    }
+    if (!dt_fixed && s->dt <= 0.0) {
+        double sm = lts_speed(s, L0);
+        s->dt = sm > 0.0 ? s->cfl_desired / sm : 1.0;
+    }
+    for (n = 0; n < nsteps; ++n) {
+        double dt, nu, cm, bm;
+        if (s->t >= s->t_end) break;
+        dt = dt_fixed ? dt_fixed[n] : s->dt;
+        if (!dt_fixed && s->t + dt > s->t_end) dt = s->t_end - s->t;
+        for (;;) {
+            for (k = 0; k < s->n_leaves; ++k)
+                for (f = 0; f < 3; ++f) memcpy(save + ((size_t)k * 3 + f) * cells, s->leaves[k].q[f], sizeof(double) * cells);
+            cm = s->clamp_mass; bm = s->bnd_mass;
+            nu = lts_macro(s, dt, L0, L1, act, prev, gacc);
+            if (nu > s->cfl_max) {
+                for (k = 0; k < s->n_leaves; ++k)
+                    for (f = 0; f < 3; ++f) memcpy(s->leaves[k].q[f], save + ((size_t)k * 3 + f) * cells, sizeof(double) * cells);
+                s->clamp_mass = cm; s->bnd_mass = bm;
+                if (dt_fixed) { n = -1; break; }
+                s->rejected++;
+                dt = dt * s->cfl_desired / nu;
+                continue;
+            }
+            break;
+        }
+        if (n < 0) break;
+        if (nu_out) nu_out[n] = nu;
+        if (dt_out) dt_out[n] = dt;
+        s->t += dt;
+        s->steps++;
+        s->dt = nu > 0.0 ? dt * s->cfl_desired / nu : dt;
+    }
+    for (k = 0; k < s->n_leaves; ++k) {
+        for (f = 0; f < 3; ++f) free(prev[k][f]);
+        free(prev[k]);
+        free(gacc[k]);
+    }
+    free(prev); free(gacc); free(act); free(save);
+    return n < 0 ? -5 : 0;
 }
 
 /* ------------------------------------------------------------------------ */
