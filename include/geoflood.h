@@ -169,6 +169,19 @@ int gf_step(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *
  * as for gf_step.  The ghosted tiles stay readable with gf_get_ghosted. */
 int gf_step_plain(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
 
+/* Local time stepping across levels: nsteps accepted macro steps, each the
+ * step of the coarsest level present; level l takes 2^(l - L0) substeps of
+ * it, fine ghosts read their coarser neighbours halfway through a coarse step
+ * as the mean of the coarse states before and after, fine face fluxes are
+ * summed over the substeps for refluxing, and a macro step is rejected (and
+ * redone, shorter) when the largest Courant number of any of its substeps
+ * exceeds cfl_max.  dt_fixed (nullable) gives each macro step's length.
+ * Every kernel of gf_step serves; work per macro step is the sum over leaves
+ * of m^2 2^(level - L0) cell updates, which out->cell_updates counts.  Gauges
+ * record once per macro step.  Errors as for gf_step (state kept at the last
+ * accepted macro step). */
+int gf_step_lts(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
+
 /* Refinement flags of every leaf of every scenario, concatenated in scenario
  * then leaf order: +1 refine, -1 coarsen, 0 keep (Section 4.1).  In order:
  * the cell criteria (depth, free-surface gradient, advancing front, speed,

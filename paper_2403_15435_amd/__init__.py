@@ -53,7 +53,7 @@ NET_PARAMS = 14579
 NET_FEATURES = 2304
 
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
-           "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain",
+           "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain", "gf_step_lts",
            "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
            "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_split", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
            "gf_net_forward", "gf_net_train_step", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     L.gf_get_ghosted.argtypes = [vp, i32, i64, i32, dp]
     L.gf_step.argtypes = [vp, i32, dp, C.POINTER(gf_step_stats)]
     L.gf_step_plain.argtypes = [vp, i32, dp, C.POINTER(gf_step_stats)]
+    L.gf_step_lts.argtypes = [vp, i32, dp, C.POINTER(gf_step_stats)]
     L.gf_tag.argtypes = [vp, C.POINTER(C.c_int8), i64, C.POINTER(i64)]
     L.gf_regrid.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(i64)]
     L.gf_mass.argtypes = [vp, i32, dp, dp, dp]
@@ -252,11 +253,13 @@ class Context:
         self._chk(self.L.gf_get_ghosted(self._p, scen, leaf, field, _dptr(out)))
         return out
 
-    def step(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None, plain: bool = False) -> gf_step_stats:
-        """nsteps accepted steps by the fused path (gf_step), or by the plain
-        comparator path (gf_step_plain) when plain is set."""
+    def step(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None, plain: bool = False,
+             lts: bool = False) -> gf_step_stats:
+        """nsteps accepted steps by the fused path (gf_step), by the plain
+        comparator path (gf_step_plain) when plain is set, or nsteps macro
+        steps of local time stepping (gf_step_lts) when lts is set."""
         st = gf_step_stats()
-        fn = self.L.gf_step_plain if plain else self.L.gf_step
+        fn = self.L.gf_step_plain if plain else (self.L.gf_step_lts if lts else self.L.gf_step)
         if dt_fixed is not None:
             d = np.ascontiguousarray(dt_fixed, dtype=np.float64)
             if d.shape[0] < nsteps:

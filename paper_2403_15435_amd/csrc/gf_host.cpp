@@ -196,6 +196,8 @@ struct gf_ctx {
     int8_t *d_flags = nullptr;
     double *d_mass = nullptr;
     TagRules *d_rules = nullptr;
+    void *d_snap = nullptr;          // local time stepping: state at the start of a macro step
+    double *d_snap_acc = nullptr;
     // gauges: points, their cells on the current mesh, device records
     struct GaugePoint { int32_t scen; double x, y; };
     std::vector<GaugePoint> gauges;
@@ -548,7 +550,7 @@ bool leaf_desc(const gf_ctx *c, int si, const Scen &s, const Leaf &L, PatchDesc 
     }
     T = RefluxTask{};
     has_task = false;
-    T.slot = L.slot; T.scen = si; T.area = P.dx * P.dy;
+    T.slot = L.slot; T.scen = si; T.area = P.dx * P.dy; T.level = L.level; T.pad = 0;
     for (int f = 0; f < 4; ++f) {
         T.reg_c[f] = -1;
         if (P.cf_role[f] != 1) continue;
@@ -582,7 +584,7 @@ int map_gauges(gf_ctx *c)
             const int32_t li = s.map.get(key_of(l, I / c->m, J / c->m));
             if (li < 0) continue;
             const Leaf &L = s.leaves[(size_t)li];
-            g[k] = GaugeDev{p.scen, L.slot, (int32_t)((J % c->m) * c->m + (I % c->m)), 0};
+            g[k] = GaugeDev{p.scen, L.slot, (int32_t)((J % c->m) * c->m + (I % c->m)), L.level};
             found = true;
         }
         if (!found) return fail(c, GF_E_INVALID, "gauge %zu: no leaf holds the point", k);
@@ -592,15 +594,15 @@ int map_gauges(gf_ctx *c)
     return GF_OK;
 }
 
-int launch_gauges(gf_ctx *c)
+int launch_gauges(gf_ctx *c, int lts)
 {
     if (c->gauges.empty() || !c->gauges_on) return GF_OK;
     const int n = (int)c->gauges.size();
     hipError_t e = c->prec == GF_FP32
         ? gf_launch_gauge_f32(c->d_gauges, n, c->d_scen, (const float *)c->q[0], (const float *)c->q[1],
-                              (const float *)c->b, c->cap, c->m, c->grec_cap, c->d_grec, c->d_gcount, c->stream)
+                              (const float *)c->b, c->cap, c->m, c->grec_cap, c->d_grec, c->d_gcount, lts, c->stream)
         : gf_launch_gauge_f64(c->d_gauges, n, c->d_scen, (const double *)c->q[0], (const double *)c->q[1],
-                              (const double *)c->b, c->cap, c->m, c->grec_cap, c->d_grec, c->d_gcount, c->stream);
+                              (const double *)c->b, c->cap, c->m, c->grec_cap, c->d_grec, c->d_gcount, lts, c->stream);
     if (e != hipSuccess) return fail(c, GF_E_HIP, "gauge launch: %s", hipGetErrorString(e));
     return GF_OK;
 }
@@ -736,12 +738,13 @@ void fill_step_args(gf_ctx *c, StepArgs<T> &a, double dt_fixed, int mode, T tau)
     a.dstab = c->d_dstab; a.stats = c->prof ? c->d_stats : nullptr;
 }
 
-int launch_reflux(gf_ctx *c)
+int launch_reflux(gf_ctx *c, int lts = 0, int tick = 0)
 {
     if (c->reflux.empty()) return GF_OK;
     RefluxArgsBase r{};
     r.tasks = c->d_reflux; r.n_tasks = (int)c->reflux.size(); r.scen = c->d_scen; r.cap = c->cap; r.tau64 = c->cfg.dry_tol;
     r.dstab = c->d_dstab;
+    r.lts = lts; r.tick = tick;
     hipError_t e;
     if (c->prec == GF_FP32)
         e = gf_launch_reflux_f32(r, (float *)c->q[0], (float *)c->q[1], (const float *)c->reg, c->cacc[0], c->cacc[1], c->dry[0], c->dry[1], c->m, c->stream);
@@ -751,7 +754,7 @@ int launch_reflux(gf_ctx *c)
     return GF_OK;
 }
 
-int launch_step(gf_ctx *c, double dt_fixed, int mode)
+int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0)
 {
     const int n = (int)c->desc.size();
     hipError_t e;
@@ -790,6 +793,7 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         StepArgs<float> a{};
         fill_step_args<float>(c, a, dt_fixed, mode, tau32(c->cfg.dry_tol));
         a.persistent = grid < n ? 1 : 0;
+        a.lts = lts; a.tick = tick;
         e = gf_launch_dry_f32(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
@@ -798,6 +802,7 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         StepArgs<double> a{};
         fill_step_args<double>(c, a, dt_fixed, mode, c->cfg.dry_tol);
         a.persistent = grid < n ? 1 : 0;
+        a.lts = lts; a.tick = tick;
         e = gf_launch_dry_f64(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
@@ -808,11 +813,45 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode)
         HIPCHK(c, hipEventRecord(c->ev[evk + 2], c->stream));
         c->prof_launches++;
     }
+    if (mode == 0 && lts) return launch_reflux(c, 1, tick);
     if (mode == 0) {
         int rc = launch_reflux(c);
-        return rc ? rc : launch_gauges(c);
+        return rc ? rc : launch_gauges(c, 0);
     }
     return GF_OK;
+}
+
+int lts_scen(gf_ctx *c, int phase)
+{
+    hipError_t e = c->prec == GF_FP32 ? gf_launch_lts_scen_f32(c->d_scen, (int)c->sc.size(), phase, c->stream)
+                                      : gf_launch_lts_scen_f64(c->d_scen, (int)c->sc.size(), phase, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "time-stepping phase launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
+int lts_copy(gf_ctx *c, int dir)
+{
+    const int n = (int)c->desc.size();
+    hipError_t e = c->prec == GF_FP32
+        ? gf_launch_lts_copy_f32(c->d_desc, n, c->d_scen, (float *)c->q[0], (float *)c->q[1], c->cacc[0], c->cacc[1],
+                                 c->bacc[0], c->bacc[1], (float *)c->d_snap, c->d_snap_acc, c->cap, dir, c->m, c->stream)
+        : gf_launch_lts_copy_f64(c->d_desc, n, c->d_scen, (double *)c->q[0], (double *)c->q[1], c->cacc[0], c->cacc[1],
+                                 c->bacc[0], c->bacc[1], (double *)c->d_snap, c->d_snap_acc, c->cap, dir, c->m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "snapshot launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
+// One macro step of local time stepping (reading R40) for every scenario that
+// takes part: snapshot, the ticks, undo where it failed, gauges.
+int lts_macro(gf_ctx *c, double dt_fixed, int kmax)
+{
+    int rc = lts_scen(c, 0);
+    if (!rc) rc = lts_copy(c, 0);
+    for (int k = 0; k < kmax && !rc; ++k) rc = launch_step(c, dt_fixed, 0, 1, k);
+    if (!rc) rc = lts_copy(c, 1);
+    if (!rc) rc = lts_scen(c, 1);
+    if (!rc) rc = launch_gauges(c, 1);
+    return rc;
 }
 
 // The plain path's work list: patch indices grouped by (scenario, level), the
@@ -948,7 +987,7 @@ int plain_attempt(gf_ctx *c, const std::vector<PlainGroup> &groups, double dt_fi
     if (rc) return rc;
     if (mode == 0 && any_accepted) {
         rc = launch_reflux(c);
-        return rc ? rc : launch_gauges(c);
+        return rc ? rc : launch_gauges(c, 0);
     }
     return GF_OK;
 }
@@ -1171,7 +1210,7 @@ void gf_destroy(gf_ctx *c)
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_rules, c->d_mass, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
                   c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats,
-                  c->d_sstage, c->d_sslots, c->d_gauges, c->d_grec, c->d_gcount};
+                  c->d_sstage, c->d_sslots, c->d_gauges, c->d_grec, c->d_gcount, c->d_snap, c->d_snap_acc};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -1513,6 +1552,86 @@ int gf_step_plain(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_sta
         }
     }
     return step_result(c, steps0, rej0, out);
+}
+
+int gf_step_lts(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *out)
+{
+    if (!c) return GF_E_INVALID;
+    if (nsteps < 0) return fail(c, GF_E_INVALID, "negative step count");
+    for (auto &s : c->sc)
+        if (!scen_ready(s)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    int rc = ensure_work(c);
+    if (rc) return rc;
+    if (!c->d_snap) {
+        HIPCHK(c, hipMalloc(&c->d_snap, 3 * (size_t)c->m * c->m * (size_t)c->cap * c->es));
+        HIPCHK(c, hipMalloc((void **)&c->d_snap_acc, 2 * sizeof(double) * (size_t)c->cap));
+    }
+    // levels present; every level starts from the common buffer; cell
+    // updates per macro step
+    int kmax = 1;
+    std::vector<int64_t> work(c->sc.size(), 0);
+    std::vector<int64_t> steps0(c->hs.size()), rej0(c->hs.size());
+    for (size_t i = 0; i < c->sc.size(); ++i) {
+        const Scen &s = c->sc[i];
+        int L0 = 99, L1 = -1;
+        for (const Leaf &L : s.leaves) { L0 = std::min(L0, L.level); L1 = std::max(L1, L.level); }
+        ScenDev &h = c->hs[i];
+        h.L0 = L0; h.L1 = L1;
+        for (int l = 0; l < 16; ++l) { h.lcur[l] = h.cur; h.lcur0[l] = h.cur; }
+        h.lts_on = 0; h.lts_fail = 0;
+        for (const Leaf &L : s.leaves) work[i] += ((int64_t)c->m * c->m) << (L.level - L0);
+        kmax = std::max(kmax, 1 << (L1 - L0));
+        h.status = 0;
+        h.target = h.steps + nsteps;
+        steps0[i] = h.steps;
+        rej0[i] = h.rejected;
+    }
+    rc = push_scen(c);
+    if (rc) return rc;
+    if (!dt_fixed) {
+        bool need = false;
+        for (auto &h : c->hs) need = need || h.dt <= 0.0;
+        if (need) {
+            rc = lts_scen(c, 0);
+            if (!rc) rc = launch_step(c, -1.0, 1, 1, 0);
+            if (!rc) rc = lts_scen(c, 1);
+            if (rc) return rc;
+        }
+    }
+    for (int k = 0; k < nsteps && !rc; ++k) rc = lts_macro(c, dt_fixed ? dt_fixed[k] : -1.0, kmax);
+    if (!rc) rc = pull_scen(c);
+    if (!rc && !dt_fixed) {
+        // rejected macro steps leave scenarios short of their target: keep going
+        for (int round = 0; round < 64 && !rc; ++round) {
+            int64_t missing = 0;
+            for (auto &h : c->hs)
+                if (h.status == 0 && h.t < h.t_end) missing = std::max<int64_t>(missing, h.target - h.steps);
+            if (missing <= 0) break;
+            for (int64_t k = 0; k < missing && !rc; ++k) rc = lts_macro(c, -1.0, kmax);
+            if (!rc) rc = pull_scen(c);
+        }
+    }
+    // every patch back to the scenario's common buffer
+    if (!rc) rc = lts_copy(c, 2);
+    if (!rc) rc = pull_scen(c);
+    c->flags_dirty = true;
+    if (rc) return rc;
+    int status = GF_OK;
+    gf_step_stats st{};
+    st.t_min = 1e300; st.t_max = -1e300; st.dt_min = 1e300; st.dt_max = -1e300;
+    for (size_t i = 0; i < c->hs.size(); ++i) {
+        const ScenDev &h = c->hs[i];
+        if (h.status != 0 && status == GF_OK) status = h.status;
+        st.steps += h.steps - steps0[i];
+        st.rejected += h.rejected - rej0[i];
+        st.cell_updates += (h.steps - steps0[i]) * work[i];
+        st.t_min = std::min(st.t_min, h.t); st.t_max = std::max(st.t_max, h.t);
+        st.dt_min = std::min(st.dt_min, h.dt); st.dt_max = std::max(st.dt_max, h.dt);
+    }
+    if (out) *out = st;
+    if (status == -5) return fail(c, GF_E_CFL, "a fixed step exceeded the maximum Courant number");
+    if (status == -6) return fail(c, GF_E_NUMERIC, "non-finite state produced");
+    return status;
 }
 
 int gf_tag(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n)

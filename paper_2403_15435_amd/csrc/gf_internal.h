@@ -41,6 +41,8 @@ struct RefluxTask {
     int32_t reg_c[4];     // register of each coarse face (m entries), -1 if the face is not coarse/fine
     int32_t reg_f[4][2];  // registers of the two fine faces covering the lower/left and upper/right half
     double area;          // coarse cell area
+    int32_t level;        // coarse patch level
+    int32_t pad;
 };
 
 // Per-scenario clock and controller state, device resident.
@@ -59,7 +61,13 @@ struct ScenDev {
     int64_t steps, rejected, target;
     int32_t accepted_last;   // 1 if the last launch accepted a step
     int32_t nan_flag;
-    unsigned long long smax_bits;  // max |s|/dx of the running attempt (double bits)
+    unsigned long long smax_bits;  // max |s|/dx of the running attempt (double bits); LTS: max Courant number
+    // local time stepping (reading R40)
+    int32_t lcur[16];        // per level: the buffer holding its current state
+    int32_t lcur0[16];       // the same at the start of the macro step
+    int32_t L0, L1;          // coarsest and finest level present
+    int32_t lts_on;          // taking part in the running macro step
+    int32_t lts_fail;        // the macro step is to be undone (rejected or failed)
 };
 
 // Refinement rules of one scenario (Section 4.1): thresholds of the cell
@@ -77,7 +85,7 @@ struct TagRules {
 
 // A gauge: the cell of the current mesh that holds the point.
 struct GaugeDev {
-    int32_t scen, slot, cell, pad;
+    int32_t scen, slot, cell, level;
 };
 
 template <typename R>
@@ -109,6 +117,8 @@ struct StepArgs {
     // fixed point of the dry update (which then writes nothing)
     uint8_t *dstab;
     unsigned long long *stats;   // [0] patches through step_kernel, [1] stable dry patches (or null)
+    int32_t lts;                 // local time stepping: the levels starting a substep at `tick` only
+    int32_t tick;
 };
 
 struct RefluxArgsBase {
@@ -118,6 +128,7 @@ struct RefluxArgsBase {
     int64_t cap;
     double tau64;
     uint8_t *dstab;          // per-slot dry-update state, cleared for corrected patches
+    int32_t lts, tick;       // local time stepping: the levels whose step ends at `tick` only
 };
 
 }  // namespace gf
@@ -140,7 +151,13 @@ struct RefluxArgsBase {
                                    hipStream_t s);                                                 \
     hipError_t gf_launch_gauge_##SFX(const gf::GaugeDev *g, int n, const gf::ScenDev *scen,        \
                                      const R *q0, const R *q1, const R *b, int64_t cap, int m,       \
-                                     int64_t rec_cap, double *rec, int64_t *count, hipStream_t s);   \
+                                     int64_t rec_cap, double *rec, int64_t *count, int lts,          \
+                                     hipStream_t s);                                                 \
+    hipError_t gf_launch_lts_scen_##SFX(gf::ScenDev *scen, int n_scen, int phase, hipStream_t s);    \
+    hipError_t gf_launch_lts_copy_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,     \
+                                        R *q0, R *q1, double *ca0, double *ca1, double *ba0,        \
+                                        double *ba1, R *snap, double *snap_acc, int64_t cap,         \
+                                        int dir, int m, hipStream_t s);                              \
     hipError_t gf_launch_mass_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,        \
                                     const R *q0, const R *q1, int64_t cap, double *out, int m,     \
                                     hipStream_t s);                                                 \
