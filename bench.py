@@ -227,6 +227,69 @@ def flood_speed_amr(steps, warmup, regrid_every=4, t_spin=1800.0):
     return out
 
 
+def lts_compare(window_steps=64):
+    """Local time stepping against the single clock on fixed AMR meshes (no
+    regrid inside the window): the valley mesh (levels 0-6) and the
+    floodplain mesh at t = 30 min (levels 0-3), FP32 fused path.  Each path
+    advances the same stretch of simulated time: the single clock takes
+    `window_steps` steps, local time stepping the macro steps that cover the
+    same time.  Reported: simulated seconds per wall second, cell updates per
+    second (local time stepping updates each level at its own rate, so it
+    does fewer) and the wall-time ratio."""
+    import paper_2403_15435_amd as gf
+    from paper_2403_15435_amd import inputs
+    out = {}
+    cases = []
+    sc = inputs.v_valley()
+    base = gf.Context([sc], precision=gf.GF_FP32, max_patches=48000)
+    base.set_initial(0)
+    for _ in range(sc.max_level - sc.min_level):
+        base.tag()
+        base.regrid(None)
+        base.set_initial(0)
+    cases.append(("valley", sc, base.leaves(0), base.state(0), 4000.0, 48000))
+    base.close()
+    fs = inputs.flood_speed()
+    base = gf.Context([fs], precision=gf.GF_FP32, max_patches=8192)
+    base.set_initial(0)
+    while base.time(0)[0] < 1800.0:
+        base.tag()
+        base.regrid(None)
+        base.step(4)
+    cases.append(("floodplain", fs, base.leaves(0), base.state(0), base.time(0)[0], 8192))
+    base.close()
+    for name, sc, leaves, state, t0, cap in cases:
+        res = {"leaves": int(leaves.shape[0]), "levels": np.bincount(leaves[:, 1]).tolist()}
+        for path in ("single_clock", "lts"):
+            ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=cap)
+            ctx.set_leaves(0, leaves)
+            ctx.set_state(0, state[:, :3])
+            ctx.set_time(0, t0)
+            ctx.autotune(steps=3)
+            lts = path == "lts"
+            ctx.step(2, lts=lts)           # warm-up (first use of each launch shape)
+            t1 = ctx.time(0)[0]
+            _sync()
+            a = time.perf_counter()
+            if not lts:
+                st = ctx.step(window_steps)
+                cells = int(st.cell_updates)
+            else:
+                cells = 0
+                while ctx.time(0)[0] - t1 < res["single_clock"]["sim_s"]:
+                    cells += int(ctx.step(1, lts=True).cell_updates)
+            _sync()
+            wall = time.perf_counter() - a
+            sim = ctx.time(0)[0] - t1
+            res[path] = {"sim_s": sim, "wall_s": wall, "sim_s_per_wall_s": sim / wall, "cell_updates_per_s": cells / wall,
+                         "steps": int(ctx.time(0)[2])}
+            ctx.close()
+        res["lts_speedup_sim_time"] = res["lts"]["sim_s_per_wall_s"] / res["single_clock"]["sim_s_per_wall_s"]
+        print(f"[bench] lts {name}: {res}", file=sys.stderr, flush=True)
+        out[name] = res
+    return out
+
+
 def ensemble(steps, warmup, n_scen=256):
     """The batched workload: 256 independent dam breaks on seeded fractal
     terrain (grids of 64^2 to 512^2 cells as 32 x 32 patches, n ~ U[0.02,
@@ -449,7 +512,8 @@ def main():
     ap.add_argument("--amr-steps", type=int, default=400, help="steps of each AMR valley run (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=200, help="steps of each ensemble run (0: skip)")
     ap.add_argument("--flood-steps", type=int, default=400, help="steps of each floodplain AMR run (0: skip)")
-    ap.add_argument("--only", choices=["valley", "ensemble", "learned", "flood"], default=None,
+    ap.add_argument("--lts-steps", type=int, default=64, help="single-clock steps of the local-time-stepping window (0: skip)")
+    ap.add_argument("--only", choices=["valley", "ensemble", "learned", "flood", "lts"], default=None,
                     help="run only this extra workload and print its section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM byte counters)")
@@ -465,6 +529,9 @@ def main():
         return
     if args.only == "ensemble":
         print(json.dumps(ensemble(args.ensemble_steps, 10)))
+        return
+    if args.only == "lts":
+        print(json.dumps(lts_compare(args.lts_steps)))
         return
     if args.only == "flood":
         print(json.dumps(flood_speed_amr(args.flood_steps, 40)))
@@ -519,6 +586,7 @@ def main():
     amr = guarded(valley_amr, args.amr_steps, 40) if args.amr_steps > 0 else None
     ens = guarded(ensemble, args.ensemble_steps, 10) if args.ensemble_steps > 0 else None
     flood = guarded(flood_speed_amr, args.flood_steps, 40) if args.flood_steps > 0 else None
+    ltsc = guarded(lts_compare, args.lts_steps) if args.lts_steps > 0 else None
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sc)
@@ -557,6 +625,7 @@ def main():
         "amr_valley": amr,
         "ensemble": ens,
         "amr_floodplain": flood,
+        "local_time_stepping": ltsc,
     }
     print(json.dumps(line))
 

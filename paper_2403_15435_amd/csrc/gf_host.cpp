@@ -1184,7 +1184,7 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     ok = ok && alloc((void **)&c->d_queue, 64) && alloc((void **)&c->dry[0], (size_t)c->cap) &&
          alloc((void **)&c->dry[1], (size_t)c->cap);
     ok = ok && alloc((void **)&c->d_wet, sizeof(int32_t) * (size_t)c->cap) && alloc((void **)&c->d_wet_count, 64);
-    ok = ok && alloc((void **)&c->d_dstab, (size_t)c->cap) && alloc((void **)&c->d_stats, 64);
+    ok = ok && alloc((void **)&c->d_dstab, (size_t)c->cap) && alloc((void **)&c->d_stats, 8 * 8 * 65);
     ok = ok && alloc((void **)&c->d_rules, sizeof(TagRules) * c->sc.size());
     if (!ok) {
         gf_destroy(c);
@@ -2491,11 +2491,15 @@ int gf_profile_split(gf_ctx *c, double *ms_dry, double *ms_step)
 int gf_profile_patches(gf_ctx *c, int64_t *full_updates, int64_t *stable_dry)
 {
     if (!c) return GF_E_INVALID;
-    unsigned long long v[2] = {0, 0};
-    HIPCHK(c, hipMemcpyAsync(v, c->d_stats, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    // [0] patches through the step kernel; [8 (1 + k)], k < 64: stable dry
+    // patches counted by the dry kernel's workgroups k mod 64
+    std::vector<unsigned long long> v(8 * 65, 0);
+    HIPCHK(c, hipMemcpyAsync(v.data(), c->d_stats, sizeof(unsigned long long) * v.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    unsigned long long st = 0;
+    for (int k = 1; k <= 64; ++k) st += v[8 * (size_t)k];
     if (full_updates) *full_updates = (int64_t)v[0];
-    if (stable_dry) *stable_dry = (int64_t)v[1];
+    if (stable_dry) *stable_dry = (int64_t)st;
     return GF_OK;
 }
 
@@ -2505,7 +2509,7 @@ int gf_profile_enable(gf_ctx *c, int32_t on)
     if (on && !c->prof) {
         c->prof_launches = 0;
         c->prof_ms = 0.0;
-        HIPCHK(c, hipMemsetAsync(c->d_stats, 0, 2 * sizeof(unsigned long long), c->stream));
+        HIPCHK(c, hipMemsetAsync(c->d_stats, 0, 8 * 8 * 65, c->stream));
     }
     c->prof = on != 0;
     return GF_OK;
