@@ -63,18 +63,29 @@ def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False,
         # launch shape from the tuner (state restored after its trials)
         tuned = ctx.autotune(steps=5)
     torch.cuda.synchronize()
-    ctx.profile_enable(True)
+    # the timed run is not instrumented; a second run of the same window
+    # (state and clock restored) records per-launch kernel times with events
+    state0 = ctx.state(0)[:, :3]
+    t_0, dt_0 = ctx.time(0)[:2]
     t0 = time.perf_counter()
     st = ctx.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    cells = int(st.cell_updates)
+    ctx.set_state(0, state0)
+    ctx.set_time(0, t_0, dt_0)
+    ctx.profile_enable(True)
+    t1 = time.perf_counter()
+    st2 = ctx.step(steps)
+    torch.cuda.synchronize()
+    wall_prof = time.perf_counter() - t1
     launches, ms = ctx.profile_read()
     ms_dry, ms_step = ctx.profile_split()
     full, stable = ctx.profile_patches()
     ctx.profile_enable(False)
-    cells = int(st.cell_updates)
+    assert int(st2.cell_updates) == cells
     mass = ctx.mass(0)
-    out = {"wall": wall, "cell_updates": cells, "steps": int(st.steps), "launches": launches,
+    out = {"wall": wall, "wall_profiled": wall_prof, "cell_updates": cells, "steps": int(st.steps), "launches": launches,
            "kernel_ms": ms, "dry_kernel_ms": ms_dry, "step_kernel_ms": ms_step,
            "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads(), "tuned": tuned,
            "full_patch_updates": full, "stable_dry_patches": stable}
