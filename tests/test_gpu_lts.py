@@ -125,3 +125,46 @@ def test_lts_then_gf_step_continues(orc):
     _, d2 = o.advance(5, return_dt=True)
     ctx.step(len(d2), d2)
     assert np.array_equal(ctx.state(0)[:, :3], o.state()[:, :3])
+
+
+def test_two_scenarios_with_different_level_spans(orc):
+    """One context, two scenarios: a three-level AMR dam break (four ticks per
+    macro step) and a single-level reservoir (one tick): each follows its own
+    oracle bit for bit, clocks and rejections included."""
+    a = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+    a.min_level, a.max_level = 1, 3
+    b = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=8, radius=300.0)
+    oa = orc.Oracle(a, leaves=amr_mesh_16())
+    ob = orc.Oracle(b)
+    init_oracle(oa, a)
+    init_oracle(ob, b)
+    ctx = gf.Context([a, b], precision=gf.GF_FP64, max_patches=256)
+    ctx.set_leaves(0, oa.leaves())
+    ctx.set_state(0, oa.state()[:, :3])
+    ctx.set_state(1, ob.state()[:, :3])
+    ctx.step(12, lts=True)
+    oa.advance(12, lts=True)
+    ob.advance(12, lts=True)
+    for k, o in ((0, oa), (1, ob)):
+        t, dt, steps, rej = ctx.time(k)
+        assert (t, dt, steps, rej) == (o.t, o.dt, o.steps, o.rejected), k
+        assert np.array_equal(ctx.state(k)[:, :3], o.state()[:, :3]), k
+
+
+def test_gauges_record_each_macro_step(orc):
+    """A gauge in a fine leaf and one in a coarse leaf: one record per
+    accepted macro step, equal to the oracle's cell after that macro step."""
+    from test_gpu_parity import _gauge_cell
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=3, radius=500.0)
+    sc.min_level, sc.max_level = 1, 3
+    o, ctx = _pair(orc, sc, amr_mesh_16())
+    pts = [(0, 310.0, 1720.0), (0, 1500.0, 600.0), (0, 1000.0, 1000.0)]
+    ctx.set_gauges(pts, cap=32)
+    want = [[] for _ in pts]
+    for k in range(8):
+        _, d = o.advance(1, return_dt=True, lts=True)
+        ctx.step(1, list(d), lts=True)
+        for g, (_, x, y) in enumerate(pts):
+            want[g].append((o.t,) + _gauge_cell(sc, o.leaves(), o.state(), x, y))
+    for g in range(len(pts)):
+        assert np.array_equal(ctx.gauge(g), np.array(want[g])), g
