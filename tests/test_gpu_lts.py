@@ -168,3 +168,39 @@ def test_gauges_record_each_macro_step(orc):
             want[g].append((o.t,) + _gauge_cell(sc, o.leaves(), o.state(), x, y))
     for g in range(len(pts)):
         assert np.array_equal(ctx.gauge(g), np.array(want[g])), g
+
+
+def test_valley_outflow_amr_and_t_end(orc):
+    """The small inflow valley (extrapolation outflow) refined by the plain
+    tagger to levels 1 and 2, then macro steps to a t_end that truncates the
+    last one: clocks, budget and state bit for bit with the oracle."""
+    sc = inputs.v_valley(level_max=2, m=16, mi=4, mj=2, lx=4000.0, ly=2000.0, dem_level=2, init_level=0)
+    sc.min_level = 0
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    for _ in range(2):
+        o.regrid(o.tag())
+        init_oracle(o, sc)
+    assert len(set(o.leaves()[:, 1].tolist())) == 2
+    o.set_time(4000.0)
+    t_end = 4000.0 + 37.3
+    sc2 = inputs.v_valley(level_max=2, m=16, mi=4, mj=2, lx=4000.0, ly=2000.0, dem_level=2, init_level=0)
+    sc2.min_level, sc2.t_end = 0, t_end
+    o2 = orc.Oracle(sc2, leaves=o.leaves())
+    o2.set_state(o.state())
+    o2.set_time(4000.0)
+    ctx = gf.Context([sc2], precision=gf.GF_FP64, max_patches=512)
+    ctx.set_leaves(0, o2.leaves())
+    ctx.set_state(0, o2.state()[:, :3])
+    ctx.set_time(0, 4000.0)
+    m0 = ctx.mass(0)
+    st = ctx.step(1000, lts=True)
+    o2.advance(1000, lts=True)
+    t, dt, steps, rej = ctx.time(0)
+    assert t == t_end == o2.t
+    assert (steps, rej) == (o2.steps, o2.rejected)
+    assert st.steps == steps
+    assert np.array_equal(ctx.state(0)[:, :3], o2.state()[:, :3])
+    M = ctx.mass(0)
+    assert M[2] - m0[2] != 0.0
+    assert abs((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) <= 1e-12 * M[0]
