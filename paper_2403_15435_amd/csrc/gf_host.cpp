@@ -211,6 +211,14 @@ struct gf_ctx {
     // host mirrors
     std::vector<PatchDesc, PinnedAlloc<PatchDesc>> desc;
     std::vector<RefluxTask> reflux;
+    // descriptor reuse across a regrid: the descriptors and reflux tasks
+    // before it, by slot, and the slots it freed.  A leaf that kept its slot
+    // and none of whose halo sources was freed has the same descriptor.
+    bool reuse = false;
+    std::vector<PatchDesc, PinnedAlloc<PatchDesc>> old_desc;
+    std::vector<RefluxTask> old_reflux;
+    std::vector<int32_t> old_at, old_task_at;
+    std::vector<char> freed_mark;
     std::vector<ScenDev> hs;
     std::vector<int8_t> last_flags;
     bool topo_dirty = true;
@@ -631,9 +639,25 @@ int rebuild_work(gf_ctx *c)
             while (sp + 1 < first.size() && first[sp + 1].second <= g) ++sp;
             const int si = first[sp].first;
             const Scen &s = c->sc[(size_t)si];
+            const Leaf &L = s.leaves[(size_t)(g - first[sp].second)];
+            if (c->reuse) {
+                const int32_t o = c->old_at[(size_t)L.slot];
+                if (o >= 0) {
+                    const PatchDesc &Q = c->old_desc[(size_t)o];
+                    bool same = true;
+                    for (int r = 0; r < 12 && same; ++r)
+                        if (Q.src[r].kind != HK_PHYS && c->freed_mark[(size_t)Q.src[r].slot]) same = false;
+                    if (same) {
+                        c->desc[(size_t)g] = Q;
+                        const int32_t ti = c->old_task_at[(size_t)L.slot];
+                        has[(size_t)g] = ti >= 0;
+                        if (ti >= 0) task[(size_t)g] = c->old_reflux[(size_t)ti];
+                        continue;
+                    }
+                }
+            }
             bool ht = false;
-            if (!leaf_desc(c, si, s, s.leaves[(size_t)(g - first[sp].second)], c->desc[(size_t)g], task[(size_t)g], ht, buf,
-                           sizeof buf)) {
+            if (!leaf_desc(c, si, s, L, c->desc[(size_t)g], task[(size_t)g], ht, buf, sizeof buf)) {
                 errs[(size_t)t] = buf;
                 err_at[(size_t)t] = g;
                 return;
@@ -1841,10 +1865,21 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
         if (e != hipSuccess) return fail(c, GF_E_HIP, "transfer launch: %s", hipGetErrorString(e));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    // the descriptors of leaves that kept their slot and their sources carry over
+    c->old_at.assign((size_t)c->cap, -1);
+    c->old_task_at.assign((size_t)c->cap, -1);
+    c->freed_mark.assign((size_t)c->cap, 0);
+    for (size_t g = 0; g < c->desc.size(); ++g) c->old_at[(size_t)c->desc[g].slot] = (int32_t)g;
+    for (size_t t = 0; t < c->reflux.size(); ++t) c->old_task_at[(size_t)c->reflux[t].slot] = (int32_t)t;
+    for (int32_t sl : freed) c->freed_mark[(size_t)sl] = 1;
+    std::swap(c->desc, c->old_desc);
+    std::swap(c->reflux, c->old_reflux);
+    c->reuse = true;
     for (int32_t sl : freed) give_slot(c, sl);
     c->topo_dirty = true;
     c->flags_dirty = true;
     rc = ensure_work(c);
+    c->reuse = false;
     if (rc) return rc;
     if (n_leaves) *n_leaves = total;
     return GF_OK;
