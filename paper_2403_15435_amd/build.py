@@ -25,15 +25,17 @@ UNITS = [
 
 
 def source_digest() -> str:
-    """SHA-256 over the kernel and host sources and the compile flags; names the
-    exact code a profile was taken on."""
+    """SHA-256 over the device-code sources (kernels and the layouts they
+    share with the host) and their compile flags; names the exact kernels a
+    profile was taken on.  Host-only code does not enter it."""
     import hashlib
     h = hashlib.sha256()
     h.update(" ".join(COMMON).encode())
     for src, extra in UNITS:
-        h.update(" ".join(extra).encode())
+        if src.endswith(".hip"):
+            h.update(" ".join(extra).encode())
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".inc", ".h", ".cpp")):
+        if name.endswith((".hip", ".inc", ".h")):
             h.update(name.encode())
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(f.read())
