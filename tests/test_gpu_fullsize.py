@@ -132,3 +132,52 @@ def test_valley_25k_leaves_fused_equals_plain_through_regrid():
     assert np.array_equal(M, b.mass(0))
     assert abs((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) <= 1e-12 * m0[0]
     assert M[2] - m0[2] != 0.0
+
+
+def test_floodplain_one_hour_on_the_benchmark_grid(orc):
+    """The floodplain on its uniform 5.2 m grid (192 x 384 cells as 6 x 12
+    patches of 32^2) from the dry start to t = 1 h: FP64 bit for bit with the
+    oracle.  On that solution, what the benchmark shows at 1 h: the inflow
+    volume within 1% of the hydrograph's integral (times the inlet cells'
+    length over 20 m), depths along the horizontal transect 7 m above the
+    axis and along the 45-degree transect within 2 cm of each other from 50 m
+    out (the paper finds the only discrepancy next to the inlet), fronts
+    (h > 1 cm) within two cells."""
+    sc = inputs.flood_speed(level_max=0, m=32, mi=6, mj=12)
+    sc.regions = None
+    sc.t_end = 3600.0
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=128)
+    _bench_shape(ctx)
+    ctx.set_state(0, o.state()[:, :3])
+    ctx.step(100000)
+    o.advance(100000)
+    t, dt, steps, rej = ctx.time(0)
+    print(f"floodplain 5.2 m: {steps} steps to t = {t:.1f} s (oracle {o.steps})", flush=True)
+    assert (t, steps, rej) == (o.t, o.steps, o.rejected) and t == 3600.0
+    st = ctx.state(0)
+    assert np.array_equal(st[:, :3], o.state()[:, :3])
+    lv = o.leaves()
+    H = np.zeros((384, 192))
+    for k, (tr, l, ix, iy) in enumerate(lv):
+        ti, tj = tr % sc.mi, tr // sc.mi
+        H[tj * 32:(tj + 1) * 32, ti * 32:(ti + 1) * 32] = st[k, 0]
+    dx = sc.dx(0)
+    M, cl, bd = ctx.mass(0)
+    ncov = sum(1 for J in range(384) if 990.0 <= (J + 0.5) * dx <= 1010.0)
+    v_in = 20.0 * 3600.0 ** 2 / (2 * 3600.0) * ncov * dx / 20.0
+    assert abs(M - cl - bd) <= 1e-12 * M
+    assert abs(bd / v_in - 1.0) <= 0.01, bd / v_in
+
+    def sample(x, y):
+        return H[np.clip((y / dx).astype(int), 0, 383), np.clip((x / dx).astype(int), 0, 191)]
+    r = np.arange(dx, 700.0, dx)
+    ha = sample(r, np.full_like(r, 1007.0))
+    hd = sample(r / np.sqrt(2.0), 1000.0 + r / np.sqrt(2.0))
+    both = (ha > 0.01) & (hd > 0.01) & (r >= 50.0)
+    print(f"transects: max |axis - diagonal| {np.abs(ha - hd)[both].max():.4f} m beyond 50 m; fronts "
+          f"{r[ha > 0.01].max():.0f} m and {r[hd > 0.01].max():.0f} m", flush=True)
+    assert both.sum() > 40
+    assert np.abs(ha - hd)[both].max() <= 0.02
+    assert abs(r[ha > 0.01].max() - r[hd > 0.01].max()) <= 2 * dx
