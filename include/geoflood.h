@@ -169,7 +169,9 @@ int gf_step(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *
  * as for gf_step.  The ghosted tiles stay readable with gf_get_ghosted. */
 int gf_step_plain(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
 
-/* Local time stepping across levels: nsteps accepted macro steps, each the
+/* Local time stepping across levels (the subcycling of ForestClaw, Section
+ * 2.1.3, on which GeoFlood builds; the paper gives no scheme, so this is the
+ * Berger-Oliger form): nsteps accepted macro steps, each the
  * step of the coarsest level present; level l takes 2^(l - L0) substeps of
  * it, fine ghosts read their coarser neighbours halfway through a coarse step
  * as the mean of the coarse states before and after, fine face fluxes are
@@ -192,7 +194,7 @@ int gf_step_lts(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_sta
  * nullable (the flags are kept for gf_regrid). */
 int gf_tag(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
 
-/* Gauges: the time series at control points that Section 5 plots.  Point k
+/* Gauges: the time series at control points that Section 5.1 plots.  Point k
  * (scenario scen[k], x = xy[2k], y = xy[2k+1], inside its domain) reads the
  * leaf cell holding it: cell floor((x - x0)/dx), floor((y - y0)/dy) at the
  * leaf's level (the last cell for a point on the far edge), found again after
