@@ -491,6 +491,31 @@ def measured_traffic():
     return (fetch + write) * 1024.0
 
 
+def profiled_kernel_us():
+    """Average durations (us) of the reservoir FP32 dry and step kernels in
+    the committed rocprofv3 kernel-trace summary; None when it was taken on
+    other kernel sources."""
+    from paper_2403_15435_amd.build import source_digest
+    path = os.path.join(ROOT, "profiles", "step_reservoir2048_kernel_stats.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if source_digest() not in text or "Reservoir, FP32:" not in text:
+        return None
+    block = text.split("Reservoir, FP32:")[1].split("\n\n")[0]
+    out = {}
+    for line in block.splitlines():
+        f = line.split()
+        if "avg_ns" not in f:
+            continue
+        avg = float(f[f.index("avg_ns") + 1]) * 1e-3
+        if "dry_kernel<32>" in line:
+            out["dry_kernel_us"] = avg
+        elif "step_kernel<32," in line and "512>" in line:
+            out["step_kernel_us"] = avg
+    return out or None
+
+
 def calibrate_copy(mib=512, reps=5):
     """Device-to-device copy of a known size, run under the same HBM byte
     counters as the step kernel to scale them: each copy reads and writes
@@ -617,6 +642,9 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6,
                      "dry_kernel_us": 1e3 * r32["dry_kernel_ms"] / max(r32["launches"], 1),
                      "step_kernel_us": 1e3 * r32["step_kernel_ms"] / max(r32["launches"], 1),
+                     # the same kernels as rocprofv3 times them (committed summary): the events
+                     # above also hold the dispatch gap before each kernel
+                     "rocprof_kernel_us": profiled_kernel_us(),
                      "patches_full_update_per_step": r32["full_patch_updates"] / max(r32["launches"], 1),
                      "patches_stable_dry_per_step": r32["stable_dry_patches"] / max(r32["launches"], 1),
                      "step_kernel_hbm_frac": (BYTES_PER_UPDATE["f32"] * 1024 * r32["full_patch_updates"]
