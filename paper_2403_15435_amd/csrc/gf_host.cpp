@@ -837,7 +837,9 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0)
         HIPCHK(c, hipEventRecord(c->ev[evk + 2], c->stream));
         c->prof_launches++;
     }
-    if (mode == 0 && lts) return launch_reflux(c, 1, tick);
+    // level l ends its step at tick k when 2^(L1 - l) divides k + 1, and only
+    // levels below the finest have reflux tasks: none end where k + 1 is odd
+    if (mode == 0 && lts) return ((tick + 1) & 1) ? GF_OK : launch_reflux(c, 1, tick);
     if (mode == 0) {
         int rc = launch_reflux(c);
         return rc ? rc : launch_gauges(c, 0);
