@@ -198,6 +198,8 @@ struct gf_ctx {
     TagRules *d_rules = nullptr;
     void *d_snap = nullptr;          // local time stepping: state at the start of a macro step
     double *d_snap_acc = nullptr;
+    int32_t *d_lperm = nullptr;      // patches by level, finest first (one clock span for all scenarios)
+    std::vector<int32_t> lts_count;  // patches within d levels of the finest, d = 0, 1, ...
     // gauges: points, their cells on the current mesh, device records
     struct GaugePoint { int32_t scen; double x, y; };
     std::vector<GaugePoint> gauges;
@@ -778,7 +780,7 @@ int launch_reflux(gf_ctx *c, int lts = 0, int tick = 0)
     return GF_OK;
 }
 
-int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0)
+int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0, int n_listed = -1)
 {
     const int n = (int)c->desc.size();
     hipError_t e;
@@ -818,7 +820,9 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0)
         fill_step_args<float>(c, a, dt_fixed, mode, tau32(c->cfg.dry_tol));
         a.persistent = grid < n ? 1 : 0;
         a.lts = lts; a.tick = tick;
-        e = gf_launch_dry_f32(a, c->m, c->stream);
+        if (n_listed >= 0) a.wet_list = c->d_lperm;
+        e = n_listed >= 0 ? hipMemsetD32Async((hipDeviceptr_t)c->d_wet_count, n_listed, 1, c->stream)
+                          : gf_launch_dry_f32(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f32(a, c->m, c->step_threads, grid, c->stream);
@@ -827,7 +831,9 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0)
         fill_step_args<double>(c, a, dt_fixed, mode, c->cfg.dry_tol);
         a.persistent = grid < n ? 1 : 0;
         a.lts = lts; a.tick = tick;
-        e = gf_launch_dry_f64(a, c->m, c->stream);
+        if (n_listed >= 0) a.wet_list = c->d_lperm;
+        e = n_listed >= 0 ? hipMemsetD32Async((hipDeviceptr_t)c->d_wet_count, n_listed, 1, c->stream)
+                          : gf_launch_dry_f64(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f64(a, c->m, c->step_threads, grid, c->stream);
@@ -873,7 +879,18 @@ int lts_macro(gf_ctx *c, double dt_fixed, int kmax)
 {
     int rc = lts_scen(c, 0);
     if (!rc) rc = lts_copy(c, 0);
-    for (int k = 0; k < kmax && !rc; ++k) rc = launch_step(c, dt_fixed, 0, 1, k);
+    for (int k = 0; k < kmax && !rc; ++k) {
+        // with one clock span for every scenario, the patches starting a
+        // substep at tick k are those within ctz(k) levels of the finest: a
+        // prefix of the list by level (all of it at k = 0)
+        int n = -1;
+        if (!c->lts_count.empty()) {
+            const size_t d = k == 0 ? c->lts_count.size() - 1
+                                    : std::min<size_t>((size_t)__builtin_ctz((unsigned)k), c->lts_count.size() - 1);
+            n = c->lts_count[d];
+        }
+        rc = launch_step(c, dt_fixed, 0, 1, k, n);
+    }
     if (!rc) rc = lts_copy(c, 1);
     if (!rc) rc = lts_scen(c, 1);
     if (!rc) rc = launch_gauges(c, 1);
@@ -1236,7 +1253,8 @@ void gf_destroy(gf_ctx *c)
                   c->d_desc, c->d_reflux, c->d_scen, c->d_counter, c->d_flags, c->d_rules, c->d_mass, c->d_xfer,
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
                   c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats,
-                  c->d_sstage, c->d_sslots, c->d_gauges, c->d_grec, c->d_gcount, c->d_snap, c->d_snap_acc};
+                  c->d_sstage, c->d_sslots, c->d_gauges, c->d_grec, c->d_gcount, c->d_snap, c->d_snap_acc,
+                  c->d_lperm};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -1612,6 +1630,30 @@ int gf_step_lts(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats
         steps0[i] = h.steps;
         rej0[i] = h.rejected;
     }
+    // the patch list by level, finest first, when every scenario spans the
+    // same number of levels (then the ticks agree)
+    c->lts_count.clear();
+    {
+        bool same = true;
+        for (size_t i = 1; i < c->hs.size(); ++i)
+            same = same && c->hs[i].L1 - c->hs[i].L0 == c->hs[0].L1 - c->hs[0].L0;
+        if (same && !c->desc.empty()) {
+            const int span = c->hs[0].L1 - c->hs[0].L0;
+            std::vector<int32_t> perm;
+            perm.reserve(c->desc.size());
+            c->lts_count.assign((size_t)span + 1, 0);
+            for (int d = 0; d <= span; ++d) {
+                for (size_t g = 0; g < c->desc.size(); ++g) {
+                    const PatchDesc &P = c->desc[g];
+                    if (c->hs[(size_t)P.scen].L1 - P.level == d) perm.push_back((int32_t)g);
+                }
+                c->lts_count[(size_t)d] = (int32_t)perm.size();
+            }
+            if (!c->d_lperm) HIPCHK(c, hipMalloc((void **)&c->d_lperm, sizeof(int32_t) * (size_t)c->cap));
+            HIPCHK(c, hipMemcpyAsync(c->d_lperm, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
     rc = push_scen(c);
     if (rc) return rc;
     if (!dt_fixed) {
@@ -1619,7 +1661,7 @@ int gf_step_lts(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats
         for (auto &h : c->hs) need = need || h.dt <= 0.0;
         if (need) {
             rc = lts_scen(c, 0);
-            if (!rc) rc = launch_step(c, -1.0, 1, 1, 0);
+            if (!rc) rc = launch_step(c, -1.0, 1, 1, 0, c->lts_count.empty() ? -1 : c->lts_count.back());
             if (!rc) rc = lts_scen(c, 1);
             if (rc) return rc;
         }
