@@ -20,23 +20,30 @@
  *     levels, effective resolution: Section 4;
  *   - inflow ghost cells from eq. (riemann) / eq. (2-shock) by Newton:
  *     Section 5.1.1 (Test Case 1 set-up);
- *   - depth/gradient refinement criteria: Section 4.1 ("GeoFlood refinement
- *     criteria"); integral-preserving topography: Section 6.2.
- * Where the paper is silent the numbered readings (R1..R40) of the design
- * notes are implemented; each function names the reading it takes.
+ *   - refinement criteria (depth, gradient, front, velocity, velocity-depth
+ *     product, flood-source regions, flow grades): Section 4.1;
+ *     integral-preserving topography: Section 6.2;
+ *   - local time stepping across levels (the subcycling of ForestClaw,
+ *     Section 2.1.3, in the Berger-Oliger form).
+ * Where the paper is silent, numbered readings (R1..R40) are taken; each
+ * function states the reading it implements.
  *
  * Parity status per function (what pins it, see tests/):
  *   riemann()              pinned: Hugoniot single-wave, wave-sum identity,
  *                          lake at rest, mirror/wall, exact 1D solutions
- *   limiter / transverse   parity unpinned beyond invariants (x<->y and
- *                          y-invariance symmetry, lake at rest, mass,
- *                          Ritter/exact-solution convergence)
+ *   limiter / transverse   pinned by invariants (x<->y and y-invariance
+ *                          symmetry, lake at rest, mass), Ritter and exact
+ *                          1D convergence, second-order convergence on a
+ *                          smooth hump
  *   ghost fill, reflux     pinned by lake at rest and mass on AMR meshes,
  *                          AMR-vs-uniform error
  *   friction               pinned: closed form on uniform flow
  *   inflow Newton          pinned: bisection root, residual
  *   pyramid                pinned: parent = mean(children), linear DEM exact
  *   regrid / balance       pinned: naive fixed point, conservation
+ *   tagging (R20, R20')    pinned: planted cells decided by hand per rule
+ *   local time stepping    pinned: single level = plain step, free stream,
+ *                          lake at rest, budget, accelerating plane, hump
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction).
  */
