@@ -773,3 +773,39 @@ def test_calls_out_of_order(orc):
     with pytest.raises(gf.GFError) as e:
         ctx.set_leaves(0, np.array([[0, 3, 0, 0]], np.int32))
     assert e.value.code == gf.GF_E_INVALID
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_degenerate_domains(orc, prec):
+    """Degenerate inputs: a domain with no water at all (no patch listed, the
+    step length falls back to 1 s, nothing moves, the clock advances), and a
+    domain of a single patch with walls on all sides; both as the oracle."""
+    dry = inputs.reservoir_fractal(level=1, m=16, L=2000.0, seed=5, radius=300.0)
+    dry.eta_fn = lambda X, Y, b: b - 1.0
+    o = orc.Oracle(dry)
+    init_oracle(o, dry)
+    ctx = gf.Context([dry], precision=prec, max_patches=16)
+    ctx.set_state(0, o.state()[:, :3])
+    st = ctx.step(5)
+    o.advance(5)
+    t, dt, steps, rej = ctx.time(0)
+    assert (t, steps, rej) == (o.t, o.steps, o.rejected) == (5.0, 5, 0)
+    assert st.cell_updates == 5 * 4 * 256
+    assert not ctx.state(0)[:, :3].any()
+
+    one = inputs.reservoir_fractal(level=0, m=32, L=500.0, seed=6, radius=120.0, h_res=5.0)
+    o = orc.Oracle(one)
+    f32 = prec == gf.GF_FP32
+    if f32:
+        o.set_bathy_f32(True)
+    init_oracle(o, one, "f32" if f32 else "f64")
+    ctx = gf.Context([one], precision=prec, max_patches=1)
+    gpu_init_like(ctx, o, "f32" if f32 else "f64")
+    _, dts = o.advance(15, return_dt=True)
+    ctx.step(len(dts), dts)
+    assert ctx.leaves(0).shape[0] == 1
+    if not f32:
+        assert np.array_equal(ctx.state(0)[:, :3], o.state()[:, :3])
+    else:
+        rel, front = check_fp32(one, o.leaves(), ctx.state(0), o.state(), 0)
+        assert rel <= 2e-5 and front <= 1e-3
