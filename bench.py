@@ -63,30 +63,29 @@ def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False,
         # launch shape from the tuner (state restored after its trials)
         tuned = ctx.autotune(steps=5)
     torch.cuda.synchronize()
-    # the timed run is not instrumented; a second run of the same window
-    # (state and clock restored) records per-launch kernel times with events
+    # the timed run: HIP events on the library's stream bracket its launches
+    # (nothing is queued between the kernels); a second run of the same window
+    # (state and clock restored) has the kernels count patches
     state0 = ctx.state(0)[:, :3]
     t_0, dt_0 = ctx.time(0)[:2]
+    ctx.profile_enable(True)
     t0 = time.perf_counter()
     st = ctx.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    launches, ms = ctx.profile_read()
+    ctx.profile_enable(False)
     cells = int(st.cell_updates)
     ctx.set_state(0, state0)
     ctx.set_time(0, t_0, dt_0)
-    ctx.profile_enable(True)
-    t1 = time.perf_counter()
+    ctx.profile_enable(False, patches=True)
     st2 = ctx.step(steps)
     torch.cuda.synchronize()
-    wall_prof = time.perf_counter() - t1
-    launches, ms = ctx.profile_read()
-    ms_dry, ms_step = ctx.profile_split()
     full, stable = ctx.profile_patches()
     ctx.profile_enable(False)
     assert int(st2.cell_updates) == cells
     mass = ctx.mass(0)
-    out = {"wall": wall, "wall_profiled": wall_prof, "cell_updates": cells, "steps": int(st.steps), "launches": launches,
-           "kernel_ms": ms, "dry_kernel_ms": ms_dry, "step_kernel_ms": ms_step,
+    out = {"wall": wall, "cell_updates": cells, "steps": int(st.steps), "launches": launches, "kernel_ms": ms,
            "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads(), "tuned": tuned,
            "full_patch_updates": full, "stable_dry_patches": stable}
     if wet_fraction:
@@ -611,7 +610,6 @@ def main():
                "fp32_cell_updates_per_s": w32["cell_updates"] / w32["wall"],
                "fp64_cell_updates_per_s": w64["cell_updates"] / w64["wall"],
                "fp32_step_us": wl * 1e6,
-               "fp32_step_kernel_us": 1e3 * w32["step_kernel_ms"] / max(w32["launches"], 1),
                "fp32_hbm_frac": BYTES_PER_UPDATE["f32"] * 4096 * 1024 / wl / 1e9 / HBM_PEAK_GBS,
                "step_threads": w32["step_threads"]}
     cups32 = r32["cell_updates"] / r32["wall"]
@@ -620,6 +618,8 @@ def main():
     cells_per_launch = 4096 * 32 * 32
     avg_launch_s = r32["kernel_ms"] / max(r32["launches"], 1) / 1e3
     achieved = BYTES_PER_UPDATE["f32"] * cells_per_launch / avg_launch_s / 1e9
+    rp_us = profiled_kernel_us()
+    rp_step = rp_us["dry_kernel_us"] + rp_us["step_kernel_us"] if rp_us and len(rp_us) == 2 else None
     amr = guarded(valley_amr, args.amr_steps, 40) if args.amr_steps > 0 else None
     ens = guarded(ensemble, args.ensemble_steps, 10) if args.ensemble_steps > 0 else None
     flood = guarded(flood_speed_amr, args.flood_steps, 40) if args.flood_steps > 0 else None
@@ -640,18 +640,19 @@ def main():
                      "traffic_unit": "HBM bytes per launch (counters x copy calibration)",
                      "algorithmic_bytes_per_launch": BYTES_PER_UPDATE["f32"] * cells_per_launch,
                      "kernel": f"one step = dry_kernel<32> + step_kernel<32,{r32['step_threads']}> (fp32)",
+                     # event pair on the library's stream around the timed launches, per step
                      "avg_launch_us": avg_launch_s * 1e6,
-                     "dry_kernel_us": 1e3 * r32["dry_kernel_ms"] / max(r32["launches"], 1),
-                     "step_kernel_us": 1e3 * r32["step_kernel_ms"] / max(r32["launches"], 1),
-                     # the same kernels as rocprofv3 times them (committed summary): the events
-                     # above also hold the dispatch gap before each kernel
-                     "rocprof_kernel_us": profiled_kernel_us(),
+                     # the same kernels as rocprofv3 times them (committed summary of this command)
+                     # and their sum, which the event figure above includes with the gaps between
+                     # launches
+                     "rocprof_kernel_us": rp_us,
+                     "rocprof_step_us": rp_step,
                      "patches_full_update_per_step": r32["full_patch_updates"] / max(r32["launches"], 1),
                      "patches_stable_dry_per_step": r32["stable_dry_patches"] / max(r32["launches"], 1),
                      "step_kernel_hbm_frac": (BYTES_PER_UPDATE["f32"] * 1024 * r32["full_patch_updates"]
                                               / max(r32["launches"], 1)
-                                              / (1e-3 * r32["step_kernel_ms"] / max(r32["launches"], 1))
-                                              / 1e9 / HBM_PEAK_GBS)},
+                                              / (1e-6 * rp_us["step_kernel_us"]) / 1e9 / HBM_PEAK_GBS
+                                              if rp_us and "step_kernel_us" in rp_us else None)},
         "fp64_plain": {"value": cupsp, "unit": "cell-updates/s", "steps": rp["steps"],
                        "path": "gf_step_plain: per step, ghost fill into ghosted tiles in HBM, one step launch per "
                                "level from them, Courant number read back and dt chosen on the host",

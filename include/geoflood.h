@@ -250,15 +250,19 @@ int gf_autotune(gf_ctx *ctx, int32_t steps, const char *cache_path, int32_t *thr
  * depend on the choice.  Errors: GF_E_INVALID for workgroups < -1. */
 int gf_set_schedule(gf_ctx *ctx, int32_t workgroups);
 
-/* Time the step with HIP events on the context stream.  A step is two
- * kernels: the classification and update of dry patches, then the full
- * update of the others.  When enabled, events bracket both; gf_profile_read
- * returns the number of steps and their summed duration (ms), and
- * gf_profile_split the two kernels' shares of the last read. */
+/* Time the steps with HIP events on the context stream.  on: bit 0 times
+ * steps, bit 1 has the kernels count patches (gf_profile_patches); 0 stops
+ * both.  A timed stretch of steps is bracketed by one event before its first
+ * launch and one at the next synchronisation of the stream (the end of a
+ * gf_step call, or gf_profile_read), so nothing is queued between the
+ * kernels; the span includes every launch of the stretch (the dry-patch and
+ * full-update kernels of each step, and reflux and gauges where a step has
+ * them).  gf_profile_read synchronises and returns the number of steps
+ * since the last read and their summed span in ms.  Errors: GF_E_INVALID
+ * for on outside 0..3. */
 int gf_profile_enable(gf_ctx *ctx, int32_t on);
 int gf_profile_read(gf_ctx *ctx, int64_t *launches, double *ms_total);
-int gf_profile_split(gf_ctx *ctx, double *ms_dry, double *ms_step);
-/* Patch counts over the profiled steps (since gf_profile_enable(ctx, 1)):
+/* Patch counts over the counted steps (since gf_profile_enable with bit 1):
  * patches that went through the full update, and dry patches found stable
  * (both state buffers already holding the dry update's result, so that
  * nothing is read or written for them).  Synchronises the stream. */

@@ -55,7 +55,7 @@ NET_FEATURES = 2304
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain", "gf_step_lts",
            "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
-           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_split", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
+           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
            "gf_net_forward", "gf_net_train_step", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
 
 _lib = None
@@ -104,7 +104,6 @@ def load(path: str = LIB_PATH):
     L.gf_autotune.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(i32), dp]
     L.gf_profile_enable.argtypes = [vp, i32]
     L.gf_profile_read.argtypes = [vp, C.POINTER(i64), dp]
-    L.gf_profile_split.argtypes = [vp, dp, dp]
     L.gf_profile_patches.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     i8p = C.POINTER(C.c_int8)
     L.gf_net_set_params.argtypes = [vp, dp, i64]
@@ -336,8 +335,10 @@ class Context:
         self._chk(self.L.gf_get_step_threads(self._p, C.byref(n)))
         return n.value
 
-    def profile_enable(self, on: bool = True):
-        self._chk(self.L.gf_profile_enable(self._p, 1 if on else 0))
+    def profile_enable(self, on: bool = True, patches: bool = False):
+        """Time steps with an event pair per stretch of launches (on) and/or
+        have the kernels count patches (patches)."""
+        self._chk(self.L.gf_profile_enable(self._p, (1 if on else 0) | (2 if patches else 0)))
 
     def profile_read(self):
         n, ms = C.c_int64(), C.c_double()
@@ -401,16 +402,10 @@ class Context:
         return st
 
     def profile_patches(self):
-        """(patches through the full update, stable dry patches skipped) since profile_enable(True)."""
+        """(patches through the full update, stable dry patches skipped) since profile_enable(patches=True)."""
         a, b = C.c_int64(), C.c_int64()
         self._chk(self.L.gf_profile_patches(self._p, C.byref(a), C.byref(b)))
         return a.value, b.value
-
-    def profile_split(self):
-        """(ms in the dry-patch kernel, ms in the full step kernel) of the last profile_read."""
-        d, w = C.c_double(), C.c_double()
-        self._chk(self.L.gf_profile_split(self._p, C.byref(d), C.byref(w)))
-        return d.value, w.value
 
     # ------------------------------------------------------------ helpers
     def set_initial(self, scen: int = 0, precision: Optional[str] = None):

@@ -162,7 +162,6 @@ struct gf_ctx {
     unsigned long long *d_stats = nullptr;   // patches through the step kernel, stable dry patches
     int32_t *d_wet = nullptr;                // wet work items of the current step
     unsigned *d_wet_count = nullptr;
-    double prof_ms_dry = 0.0, prof_ms_step = 0.0;
     unsigned *d_queue = nullptr;
     // plain path: work items grouped by (scenario, level), per-item Courant
     // data, per-scenario ranges and results
@@ -224,8 +223,10 @@ struct gf_ctx {
     std::vector<ScenDev> hs;
     std::vector<int8_t> last_flags;
     bool topo_dirty = true;
-    // profiling
-    bool prof = false;
+    // profiling: prof times the steps with an event pair per stretch of
+    // launches (ev[0] before its first step, ev[1] before the next
+    // synchronisation); prof_stats has the kernels count patches
+    bool prof = false, prof_stats = false, prof_open = false;
     std::vector<hipEvent_t> ev;
     int64_t prof_launches = 0;
     double prof_ms = 0.0;
@@ -712,11 +713,31 @@ int push_scen(gf_ctx *c)
     return GF_OK;
 }
 
+// ends an open profiling stretch (the stream has reached ev[1] once it is
+// synchronised)
+int prof_mark_end(gf_ctx *c)
+{
+    if (c->prof_open) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    return GF_OK;
+}
+
+int prof_collect(gf_ctx *c)
+{
+    if (!c->prof_open) return GF_OK;
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    c->prof_ms += ms;
+    c->prof_open = false;
+    return GF_OK;
+}
+
 int pull_scen(gf_ctx *c)
 {
+    int rc = prof_mark_end(c);
+    if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(c->hs.data(), c->d_scen, sizeof(ScenDev) * c->hs.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return GF_OK;
+    return prof_collect(c);
 }
 
 int ensure_work(gf_ctx *c)
@@ -761,7 +782,7 @@ void fill_step_args(gf_ctx *c, StepArgs<T> &a, double dt_fixed, int mode, T tau)
     a.tau = tau; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter;
     a.queue = c->d_queue; a.persistent = 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
     a.wet_list = c->d_wet; a.wet_count = c->d_wet_count;
-    a.dstab = c->d_dstab; a.stats = c->prof ? c->d_stats : nullptr;
+    a.dstab = c->d_dstab; a.stats = c->prof_stats ? c->d_stats : nullptr;
 }
 
 int launch_reflux(gf_ctx *c, int lts = 0, int tick = 0)
@@ -802,16 +823,17 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         }
         if (want > 0 && want < n) grid = want;
     }
+    // a profiled stretch of steps opens with an event before its first launch;
+    // no packet goes between the kernels of the stretch
     const bool timed = c->prof && mode == 0;
-    size_t evk = 0;
-    if (timed) {
-        evk = (size_t)c->prof_launches * 3;
-        while (c->ev.size() < evk + 3) {
+    if (timed && !c->prof_open) {
+        while (c->ev.size() < 2) {
             hipEvent_t x;
             HIPCHK(c, hipEventCreate(&x));
             c->ev.push_back(x);
         }
-        HIPCHK(c, hipEventRecord(c->ev[evk], c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        c->prof_open = true;
     }
     // dry_kernel (classification and the dry update) then step_kernel on the
     // wet list
@@ -824,7 +846,6 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         e = n_listed >= 0 ? hipMemsetD32Async((hipDeviceptr_t)c->d_wet_count, n_listed, 1, c->stream)
                           : gf_launch_dry_f32(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
-        if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f32(a, c->m, c->step_threads, grid, c->stream);
     } else {
         StepArgs<double> a{};
@@ -835,14 +856,10 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         e = n_listed >= 0 ? hipMemsetD32Async((hipDeviceptr_t)c->d_wet_count, n_listed, 1, c->stream)
                           : gf_launch_dry_f64(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
-        if (timed) HIPCHK(c, hipEventRecord(c->ev[evk + 1], c->stream));
         e = gf_launch_step_f64(a, c->m, c->step_threads, grid, c->stream);
     }
     if (e != hipSuccess) return fail(c, GF_E_HIP, "step launch: %s", hipGetErrorString(e));
-    if (timed) {
-        HIPCHK(c, hipEventRecord(c->ev[evk + 2], c->stream));
-        c->prof_launches++;
-    }
+    if (timed) c->prof_launches++;
     // level l ends its step at tick k when 2^(L1 - l) divides k + 1, and only
     // levels below the finest have reflux tasks: none end where k + 1 is odd
     if (mode == 0 && lts) return ((tick + 1) & 1) ? GF_OK : launch_reflux(c, 1, tick);
@@ -2524,6 +2541,7 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
             if (rc == GF_OK) {
                 c->prof = true;
                 c->prof_launches = 0;
+                c->prof_ms = 0.0;
                 rc = gf_step(c, steps, nullptr, nullptr);
             }
             int64_t n = 0;
@@ -2542,6 +2560,7 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
         }
     c->prof = prof0;
     c->prof_launches = 0;
+    c->prof_ms = 0.0;
     c->gauges_on = true;
     // the trials may have rewritten face records of patches the snapshot
     // holds as stable: every patch goes back to full dry updates
@@ -2556,14 +2575,6 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
     if (threads_out) *threads_out = best_nt;
     if (sched_out) *sched_out = best_sched;
     if (us_per_step_out) *us_per_step_out = best_us;
-    return GF_OK;
-}
-
-int gf_profile_split(gf_ctx *c, double *ms_dry, double *ms_step)
-{
-    if (!c) return GF_E_INVALID;
-    if (ms_dry) *ms_dry = c->prof_ms_dry;
-    if (ms_step) *ms_step = c->prof_ms_step;
     return GF_OK;
 }
 
@@ -2584,32 +2595,36 @@ int gf_profile_patches(gf_ctx *c, int64_t *full_updates, int64_t *stable_dry)
 
 int gf_profile_enable(gf_ctx *c, int32_t on)
 {
-    if (!c) return GF_E_INVALID;
-    if (on && !c->prof) {
+    if (!c || on < 0 || on > 3) return GF_E_INVALID;
+    if (c->prof_open) {
+        int rc = prof_mark_end(c);
+        if (rc) return rc;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        rc = prof_collect(c);
+        if (rc) return rc;
+    }
+    if ((on & 1) && !c->prof) {
         c->prof_launches = 0;
         c->prof_ms = 0.0;
-        HIPCHK(c, hipMemsetAsync(c->d_stats, 0, 8 * 8 * 65, c->stream));
     }
-    c->prof = on != 0;
+    if ((on & 2) && !c->prof_stats) HIPCHK(c, hipMemsetAsync(c->d_stats, 0, 8 * 8 * 65, c->stream));
+    c->prof = (on & 1) != 0;
+    c->prof_stats = (on & 2) != 0;
     return GF_OK;
 }
 
 int gf_profile_read(gf_ctx *c, int64_t *launches, double *ms_total)
 {
     if (!c) return GF_E_INVALID;
+    int rc = prof_mark_end(c);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double ms = 0.0, md = 0.0, mw = 0.0;
-    for (int64_t k = 0; k < c->prof_launches; ++k) {
-        float x = 0.f, y = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&x, c->ev[(size_t)(3 * k)], c->ev[(size_t)(3 * k + 1)]));
-        HIPCHK(c, hipEventElapsedTime(&y, c->ev[(size_t)(3 * k + 1)], c->ev[(size_t)(3 * k + 2)]));
-        md += x; mw += y; ms += (double)x + (double)y;
-    }
+    rc = prof_collect(c);
+    if (rc) return rc;
     if (launches) *launches = c->prof_launches;
-    if (ms_total) *ms_total = ms;
-    c->prof_ms_dry = md;
-    c->prof_ms_step = mw;
+    if (ms_total) *ms_total = c->prof_ms;
     c->prof_launches = 0;
+    c->prof_ms = 0.0;
     return GF_OK;
 }
 

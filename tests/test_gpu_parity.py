@@ -267,7 +267,7 @@ def test_stable_dry_patches_are_skipped_exactly(orc, prec):
     sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
     ctx = gf.Context([sc], precision=prec, max_patches=64)
     ctx.set_initial(0)
-    ctx.profile_enable(True)
+    ctx.profile_enable(False, patches=True)
     ctx.step(60)
     full, stable = ctx.profile_patches()
     ctx.profile_enable(False)
