@@ -809,3 +809,43 @@ def test_degenerate_domains(orc, prec):
     else:
         rel, front = check_fp32(one, o.leaves(), ctx.state(0), o.state(), 0)
         assert rel <= 2e-5 and front <= 1e-3
+
+
+def test_profile_window_counts_steps_and_fits_the_wall_clock():
+    """Step timing: one event pair per stretch of launches.  The step count
+    is exact, the span is positive and no longer than the host's clock around
+    the same calls, a read resets both, and timing does not change results.
+    Patch counting is a separate switch that leaves the timing off."""
+    import time
+    import torch
+    sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
+    ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=64)
+    ctx.set_initial(0)
+    ref = gf.Context([sc], precision=gf.GF_FP32, max_patches=64)
+    ref.set_initial(0)
+    ctx.step(5)
+    ref.step(5)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    st1 = ctx.step(40)
+    st2 = ctx.step(20)
+    torch.cuda.synchronize()
+    wall_ms = 1e3 * (time.perf_counter() - t0)
+    n, ms = ctx.profile_read()
+    print(f"{n} steps, {ms:.3f} ms of events, {wall_ms:.3f} ms wall", flush=True)
+    assert n == int(st1.steps) + int(st1.rejected) + int(st2.steps) + int(st2.rejected)
+    assert 0.0 < ms <= wall_ms
+    assert ctx.profile_read() == (0, 0.0)
+    ctx.profile_enable(False)
+    ref.step(60)
+    assert np.array_equal(ctx.state(0), ref.state(0))
+    # counting without timing
+    ctx.profile_enable(False, patches=True)
+    ctx.step(10)
+    full, stable = ctx.profile_patches()
+    assert full + stable > 0
+    assert ctx.profile_read() == (0, 0.0)
+    ctx.profile_enable(False)
+    with pytest.raises(gf.GFError):
+        ctx._chk(ctx.L.gf_profile_enable(ctx._p, 4))
