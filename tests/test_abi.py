@@ -38,6 +38,8 @@ def test_version_and_null_context():
     assert L.gf_create(None, None) == gf.GF_E_INVALID
     assert L.gf_step_plain(None, 1, None, None) == gf.GF_E_INVALID
     assert L.gf_profile_patches(None, None, None) == gf.GF_E_INVALID
+    assert L.gf_profile_enable(None, 1) == gf.GF_E_INVALID
+    assert L.gf_profile_read(None, None, None) == gf.GF_E_INVALID
     assert L.gf_run(None, 1, 0, 4, 16, None) == gf.GF_E_INVALID
     assert L.gf_net_collect(None, 16, 4, None, None, 0, None) == gf.GF_E_INVALID
     assert L.gf_set_gauges(None, 0, None, None, 1) == gf.GF_E_INVALID
