@@ -849,3 +849,38 @@ def test_profile_window_counts_steps_and_fits_the_wall_clock():
     ctx.profile_enable(False)
     with pytest.raises(gf.GFError):
         ctx._chk(ctx.L.gf_profile_enable(ctx._p, 4))
+
+
+def test_patch_pool_exhaustion_is_refused_cleanly():
+    """A patch pool too small for the next mesh: the regrid and a leaf list
+    beyond the pool are refused with GF_E_NOMEM before anything changes, so
+    the leaves and state stay as they were and later steps equal those of a
+    context that never tried."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=4, radius=400.0)
+    sc.min_level, sc.max_level = 1, 4
+    big = gf.Context([sc], precision=gf.GF_FP64, max_patches=400)
+    big.set_initial(0)
+    n0 = big.leaves(0).shape[0]
+    small = gf.Context([sc], precision=gf.GF_FP64, max_patches=n0 + 3)
+    small.set_initial(0)
+    flags = small.tag()
+    assert np.array_equal(flags, big.tag()) and (flags == 1).any()
+    leaves0, state0 = small.leaves(0), small.state(0)
+    with pytest.raises(gf.GFError) as err:
+        small.regrid(flags)
+    assert err.value.code == gf.GF_E_NOMEM
+    assert np.array_equal(small.leaves(0), leaves0)
+    assert np.array_equal(small.state(0), state0)
+    big.regrid(flags)
+    assert big.leaves(0).shape[0] > n0 + 3
+    with pytest.raises(gf.GFError) as err:
+        small.set_leaves(0, big.leaves(0))
+    assert err.value.code == gf.GF_E_NOMEM
+    assert np.array_equal(small.leaves(0), leaves0)
+    assert np.array_equal(small.state(0), state0)
+    ref = gf.Context([sc], precision=gf.GF_FP64, max_patches=n0 + 3)
+    ref.set_initial(0)
+    small.step(10)
+    ref.step(10)
+    assert small.time(0) == ref.time(0)
+    assert np.array_equal(small.state(0), ref.state(0))
