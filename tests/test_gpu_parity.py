@@ -884,3 +884,35 @@ def test_patch_pool_exhaustion_is_refused_cleanly():
     ref.step(10)
     assert small.time(0) == ref.time(0)
     assert np.array_equal(small.state(0), ref.state(0))
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_zero_steps_and_an_empty_regrid_change_nothing(prec):
+    """Degenerate calls: zero steps update no cell and leave clock and state
+    alone; a regrid with no patch flagged (all keep) leaves the leaves, the
+    state and the volume budget bit for bit, and stepping on equals a
+    context that made neither call."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=4, radius=400.0)
+    sc.min_level, sc.max_level = 1, 4
+    a = gf.Context([sc], precision=prec, max_patches=400)
+    a.set_initial(0)
+    a.regrid(a.tag())
+    b = gf.Context([sc], precision=prec, max_patches=400)
+    b.set_initial(0)
+    b.regrid(b.tag())
+    a.step(3)
+    b.step(3)
+    t0, s0, m0, l0 = a.time(0), a.state(0), a.mass(0), a.leaves(0)
+    st = a.step(0)
+    assert int(st.steps) == 0 and int(st.cell_updates) == 0
+    assert a.time(0) == t0 and np.array_equal(a.state(0), s0)
+    n = a.regrid(np.zeros(l0.shape[0], dtype=np.int8))
+    assert n == l0.shape[0]
+    assert np.array_equal(a.leaves(0), l0)
+    assert np.array_equal(a.state(0), s0)
+    assert np.array_equal(a.mass(0), m0)
+    a.step(10)
+    b.step(10)
+    assert a.time(0) == b.time(0)
+    assert np.array_equal(a.state(0), b.state(0))
+    assert np.array_equal(a.mass(0), b.mass(0))
