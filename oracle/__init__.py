@@ -24,24 +24,35 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, plain -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+# Compile-time variants of the oracle, for pins that compare two written-out
+# forms of one step.  "per_edge": the transverse solver splits each edge's
+# increment into the neighbouring cell separately (the form as first written
+# in the cited CTU method) instead of the cell's net normal increment.
+VARIANTS = {None: [], "per_edge": ["-DORC_TRANSVERSE_PER_EDGE"]}
 
 
-_lib = None
+def _lib_path(variant=None) -> str:
+    return _LIB if variant is None else os.path.join(_HERE, f"libgeoflood_oracle_{variant}.so")
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        build(force=False)
-        L = C.CDLL(_LIB)
+def build(force: bool = True, variant=None) -> str:
+    """Compile the oracle with gcc (no FMA contraction, plain -O2, OpenMP)."""
+    path = _lib_path(variant)
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                               "-shared", *VARIANTS[variant], "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
+
+
+_libs = {}
+
+
+def lib(variant=None):
+    if variant not in _libs:
+        build(force=False, variant=variant)
+        L = C.CDLL(_lib_path(variant))
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [_dp, _ip, _dp, C.c_int]
         L.orc_destroy.argtypes = [C.c_void_p]
@@ -83,8 +94,28 @@ def lib():
         L.orc_inflow_depth.restype = C.c_double
         L.orc_hydrograph.argtypes = [C.c_void_p, C.c_double]
         L.orc_hydrograph.restype = C.c_double
-        _lib = L
-    return _lib
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
+        L.orc_cbrt.argtypes = [C.c_double]
+        L.orc_cbrt.restype = C.c_double
+        _libs[variant] = L
+    return _libs[variant]
+
+
+def set_threads(n: int) -> int:
+    """Threads for the oracle's loops over leaves (n < 1: every core).  The
+    results do not depend on it.  Returns the count now in effect."""
+    lib().orc_set_threads(int(n))
+    return lib().orc_get_threads()
+
+
+def threads() -> int:
+    return lib().orc_get_threads()
+
+
+def cbrt(x: float) -> float:
+    """The oracle's cube root (used by the friction term)."""
+    return lib().orc_cbrt(float(x))
 
 
 def _d(a: np.ndarray):
@@ -113,15 +144,17 @@ class Oracle:
     """One scenario on the CPU oracle.  `sc` is an inputs.Scenario."""
 
     def __init__(self, sc, g: float = G_DEFAULT, tau: float = TAU_DEFAULT,
-                 cfl_desired: float = 0.9, cfl_max: float = 1.0, leaves: Optional[np.ndarray] = None):
+                 cfl_desired: float = 0.9, cfl_max: float = 1.0, leaves: Optional[np.ndarray] = None,
+                 variant=None):
         self.sc = sc
         self.m = sc.m
+        self._L = lib(variant)
         dp = np.array([sc.x0, sc.y0, sc.x1, sc.y1, g, tau, sc.manning_n, cfl_desired, cfl_max,
                        sc.inflow_lo, sc.inflow_hi, sc.tag_h_refine, sc.tag_eta_refine, sc.t_end], dtype=np.float64)
         ip = np.array([sc.mi, sc.mj, sc.m, sc.min_level, sc.max_level, *sc.bc, sc.inflow_side], dtype=np.int32)
         hy = np.array(sc.hydro if sc.hydro else [(0.0, 0.0)], dtype=np.float64).reshape(-1)
         nh = len(sc.hydro) if sc.hydro else 0
-        L = lib()
+        L = self._L
         self._p = L.orc_create(_d(dp), ip.ctypes.data_as(_ip), _d(hy), nh)
         rg = np.asarray(sc.regions if sc.regions else [(0.0,) * 6], dtype=np.float64).reshape(-1)
         gr = np.asarray(sc.grades if sc.grades else [(0.0,) * 3], dtype=np.float64).reshape(-1)
@@ -138,7 +171,7 @@ class Oracle:
     def __del__(self):
         try:
             if self._p:
-                lib().orc_destroy(self._p)
+                self._L.orc_destroy(self._p)
                 self._p = None
         except Exception:
             pass
@@ -146,31 +179,31 @@ class Oracle:
     # mesh -------------------------------------------------------------
     def set_leaves(self, leaves: np.ndarray):
         a = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
-        lib().orc_set_leaves(self._p, a.ctypes.data_as(_ip), a.shape[0])
+        self._L.orc_set_leaves(self._p, a.ctypes.data_as(_ip), a.shape[0])
 
     @property
     def n_leaves(self) -> int:
-        return lib().orc_num_leaves(self._p)
+        return self._L.orc_num_leaves(self._p)
 
     def leaves(self) -> np.ndarray:
         out = np.zeros((self.n_leaves, 4), dtype=np.int32)
-        lib().orc_get_leaves(self._p, out.ctypes.data_as(_ip))
+        self._L.orc_get_leaves(self._p, out.ctypes.data_as(_ip))
         return out
 
     # fields -----------------------------------------------------------
     def set_field(self, leaf: int, field: int, a: np.ndarray):
         a = np.ascontiguousarray(a, dtype=np.float64).reshape(self.m, self.m)
-        if lib().orc_set_field(self._p, leaf, field, _d(a)) != 0:
+        if self._L.orc_set_field(self._p, leaf, field, _d(a)) != 0:
             raise IndexError
     def get_field(self, leaf: int, field: int) -> np.ndarray:
         out = np.zeros((self.m, self.m))
-        if lib().orc_get_field(self._p, leaf, field, _d(out)) != 0:
+        if self._L.orc_get_field(self._p, leaf, field, _d(out)) != 0:
             raise IndexError
         return out
 
     def get_ghosted(self, leaf: int, field: int) -> np.ndarray:
         out = np.zeros((self.m + 4, self.m + 4))
-        lib().orc_get_ghosted(self._p, leaf, field, _d(out))
+        self._L.orc_get_ghosted(self._p, leaf, field, _d(out))
         return out
 
     def state(self) -> np.ndarray:
@@ -189,14 +222,14 @@ class Oracle:
 
     # time stepping ----------------------------------------------------
     def fill_ghosts(self):
-        lib().orc_fill_ghosts(self._p)
+        self._L.orc_fill_ghosts(self._p)
 
     def max_speed(self) -> float:
-        return lib().orc_max_speed(self._p)
+        return self._L.orc_max_speed(self._p)
 
     def step(self, dt: float) -> float:
         """One step of length dt; returns max|s|/dx.  Does not advance the clock."""
-        return lib().orc_step(self._p, dt)
+        return self._L.orc_step(self._p, dt)
 
     def advance(self, nsteps: int, dt_fixed: Optional[Sequence[float]] = None, return_dt: bool = False,
                 lts: bool = False):
@@ -208,9 +241,9 @@ class Oracle:
         s0 = self.steps
         if dt_fixed is not None:
             d = np.ascontiguousarray(dt_fixed, dtype=np.float64)
-            rc = (lib().orc_advance_lts if lts else lib().orc_advance)(self._p, nsteps, _d(d), _d(nu), _d(dts))
+            rc = (self._L.orc_advance_lts if lts else self._L.orc_advance)(self._p, nsteps, _d(d), _d(nu), _d(dts))
         else:
-            rc = (lib().orc_advance_lts if lts else lib().orc_advance)(self._p, nsteps, None, _d(nu), _d(dts))
+            rc = (self._L.orc_advance_lts if lts else self._L.orc_advance)(self._p, nsteps, None, _d(nu), _d(dts))
         if rc != 0:
             raise RuntimeError(f"oracle advance failed ({rc})")
         k = self.steps - s0
@@ -218,44 +251,44 @@ class Oracle:
 
     def set_bathy_f32(self, on: bool = True):
         """Hold the bathymetry rounded to float32 (FP32-path judging)."""
-        lib().orc_set_bathy_f32(self._p, 1 if on else 0)
+        self._L.orc_set_bathy_f32(self._p, 1 if on else 0)
 
     @property
     def t(self) -> float:
-        return lib().orc_time(self._p)
+        return self._L.orc_time(self._p)
 
     @property
     def dt(self) -> float:
-        return lib().orc_dt(self._p)
+        return self._L.orc_dt(self._p)
 
     @property
     def steps(self) -> int:
-        return lib().orc_steps(self._p)
+        return self._L.orc_steps(self._p)
 
     @property
     def rejected(self) -> int:
-        return lib().orc_rejected(self._p)
+        return self._L.orc_rejected(self._p)
 
     def set_time(self, t: float, dt: float = 0.0):
-        lib().orc_set_time(self._p, t, dt)
+        self._L.orc_set_time(self._p, t, dt)
 
     def mass(self):
         out = np.zeros(3)
-        lib().orc_mass(self._p, _d(out))
+        self._L.orc_mass(self._p, _d(out))
         return out  # mass, clamp mass, boundary inflow volume
 
     # AMR --------------------------------------------------------------
     def tag(self) -> np.ndarray:
         out = np.zeros(self.n_leaves, dtype=np.int8)
-        lib().orc_tag(self._p, out.ctypes.data_as(C.POINTER(C.c_byte)))
+        self._L.orc_tag(self._p, out.ctypes.data_as(C.POINTER(C.c_byte)))
         return out
 
     def regrid(self, flags: np.ndarray) -> int:
         f = np.ascontiguousarray(flags, dtype=np.int8)
-        return lib().orc_regrid(self._p, f.ctypes.data_as(C.POINTER(C.c_byte)))
+        return self._L.orc_regrid(self._p, f.ctypes.data_as(C.POINTER(C.c_byte)))
 
     def bathy(self, level: int, I: int, J: int) -> float:
-        return lib().orc_bathy(self._p, level, I, J)
+        return self._L.orc_bathy(self._p, level, I, J)
 
     def hydrograph(self, t: float) -> float:
-        return lib().orc_hydrograph(self._p, t)
+        return self._L.orc_hydrograph(self._p, t)

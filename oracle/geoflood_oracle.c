@@ -45,13 +45,20 @@
  *   local time stepping    pinned: single level = plain step, free stream,
  *                          lake at rest, budget, accelerating plane, hump
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction).
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no FMA
+ * contraction).  Loops over leaves run on OpenMP threads; each iteration
+ * writes only its own leaf, and the budget partials (clamp and boundary
+ * volume) are formed per leaf and summed in leaf order afterwards, so the
+ * results do not depend on the thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_WALL 0
 #define ORC_EXTRAP 1
@@ -110,6 +117,25 @@ typedef struct {
 /* ------------------------------------------------------------------------ */
 
 static inline int G(const orc_sim *s, int i, int j) { return (j + 2) * (s->m + 4) + (i + 2); }
+
+/* Threads used by the loops over leaves (n < 1: all available). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static uint64_t key_of(int level, long PI, long PJ)
 {
@@ -735,10 +761,12 @@ static void interp_coarse_to_fine(const orc_sim *s, const leaf_t *C, double *con
    states before their last update). */
 static void fill_ghosts_sel(orc_sim *s, double t, const char *act, const char *half, double ***prev)
 {
-    int m = s->m, k, i, j, f;
+    int m = s->m, k;
+#pragma omp parallel for schedule(dynamic, 4)
     for (k = 0; k < s->n_leaves; ++k) {
         leaf_t *L = &s->leaves[k];
         long ni = NI(s, L->level), nj = NJ(s, L->level);
+        int i, j, f;
         if (act && !act[k]) continue;
         for (j = -2; j < m + 2; ++j)
             for (i = -2; i < m + 2; ++i) {
@@ -1024,11 +1052,17 @@ static void correction_flux(const orc_sim *s, const edge_t *E, int e, int r, dou
 
 /* Advance every leaf by dt (ghosts must be filled).  Stores the new interior
  * into the leaves, the reflux gains into leaf->gain, the boundary mass flux
- * into s->bnd_mass, and returns max over edges of |s|/dx. */
+ * into s->bnd_mass (per-leaf partials added in leaf order), and returns max
+ * over edges of |s|/dx. */
 static double update_all(orc_sim *s, double dt, const char *act)
 {
     int m = s->m, k, ne = m + 3;
     double smax_all = 0.0;
+    double **newq = (double **)malloc(sizeof(double *) * (size_t)s->n_leaves * 3 + 1);
+    double *leaf_smax = (double *)calloc((size_t)s->n_leaves + 1, sizeof(double));
+    double *leaf_bnd = (double *)calloc((size_t)s->n_leaves + 1, sizeof(double));
+#pragma omp parallel
+    {
     size_t nedge = (size_t)(m + 2) * (size_t)ne;
     edge_t *EX = (edge_t *)malloc(sizeof(edge_t) * nedge);
     edge_t *EY = (edge_t *)malloc(sizeof(edge_t) * nedge);
@@ -1046,12 +1080,14 @@ static double update_all(orc_sim *s, double dt, const char *act)
     DPX[1] = (double *)malloc(sizeof(double) * (size_t)(m + 2) * (m + 1) * 3);
     Dx = (double *)malloc(sizeof(double) * (size_t)(m + 2) * m * 3);
     Dy = (double *)malloc(sizeof(double) * (size_t)(m + 2) * m * 3);
-    double **newq = (double **)malloc(sizeof(double *) * (size_t)s->n_leaves * 3);
-    for (k = 0; k < s->n_leaves; ++k) {
+    int kk_;
+#pragma omp for schedule(dynamic, 1)
+    for (kk_ = 0; kk_ < s->n_leaves; ++kk_) {
+        const int k = kk_;
         leaf_t *L = &s->leaves[k];
         double dx = DX(s, L->level), dy = DY(s, L->level);
         double dtdx = dt / dx, dtdy = dt / dy;
-        double sx, sy, smax;
+        double sx, sy, smax, bnd = 0.0;
         int i, j, e, r, f, c;
         long ni = NI(s, L->level), nj = NJ(s, L->level);
         newq[3 * k] = NULL;
@@ -1059,7 +1095,7 @@ static double update_all(orc_sim *s, double dt, const char *act)
         sx = sweep_solve(s, L, 0, EX);
         sy = sweep_solve(s, L, 1, EY);
         smax = sx / dx > sy / dy ? sx / dx : sy / dy;
-        if (smax > smax_all) smax_all = smax;
+        leaf_smax[k] = smax;
         memset(FX, 0, sizeof(double) * (size_t)(m + 1) * m * 3);
         memset(GY, 0, sizeof(double) * (size_t)(m + 1) * m * 3);
         memset(FXt, 0, sizeof(double) * (size_t)(m + 1) * m * 3);
@@ -1106,12 +1142,36 @@ static double update_all(orc_sim *s, double dt, const char *act)
                     if (c == 0) { ga = G(s, e, r); gb = G(s, e, r + 1); }
                     else { ga = G(s, r, e); gb = G(s, r + 1, e); }
                     /* B+ of the increment of (k, r) towards (k, r+1); B- of (k, r+1) towards (k, r) */
+#ifdef ORC_TRANSVERSE_PER_EDGE
+                    {
+                        /* each edge's increment into the cell split on its own
+                           (A+dQ - F of its left edge, A-dQ + F of its right
+                           edge), the parts then summed: the same as splitting
+                           their sum in real arithmetic (linear solver, one
+                           Roe state) */
+                        double u1[3], u2[3], d1[3], d2[3];
+                        transverse_split(s, L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
+                                         L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
+                                         &DP[((r + 1) * (m + 1) + e) * 3], 1, u1);
+                        transverse_split(s, L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
+                                         L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
+                                         &DM[((r + 1) * (m + 1) + e + 1) * 3], 1, u2);
+                        transverse_split(s, L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
+                                         L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
+                                         &DP[((r + 2) * (m + 1) + e) * 3], 0, d1);
+                        transverse_split(s, L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
+                                         L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
+                                         &DM[((r + 2) * (m + 1) + e + 1) * 3], 0, d2);
+                        for (f = 0; f < 3; ++f) { up[f] = u1[f] + u2[f]; dn[f] = d1[f] + d2[f]; }
+                    }
+#else
                     transverse_split(s, L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
                                      L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
                                      &Dn[((r + 1) * m + e) * 3], 1, up);
                     transverse_split(s, L->q[0][gb], L->q[1 + c][gb], L->q[2 - c][gb], L->b[gb],
                                      L->q[0][ga], L->q[1 + c][ga], L->q[2 - c][ga], L->b[ga],
                                      &Dn[((r + 2) * m + e) * 3], 0, dn);
+#endif
                     for (f = 0; f < 3; ++f) o[f] = -((0.5 * dtn) * (up[f] + dn[f]));
                     /* (h, normal, tangential) -> (h, hu, hv) */
                     Ft[(e * (m + 1) + r + 1) * 3 + 0] = o[0];
@@ -1190,11 +1250,21 @@ static double update_all(orc_sim *s, double dt, const char *act)
                 }
                 I = L->PI * m + ci; J = L->PJ * m + cj;
                 onb = (f == 0 && I == 0) || (f == 1 && I == ni - 1) || (f == 2 && J == 0) || (f == 3 && J == nj - 1);
-                if (onb && s->bc[f] != ORC_WALL) s->bnd_mass += own[0];
+                if (onb && s->bc[f] != ORC_WALL) bnd += own[0];
             }
         }
+        leaf_bnd[k] = bnd;
     }
-    /* commit */
+    free(EX); free(EY); free(FX); free(GY); free(FXt); free(GYt);
+    free(DMX[0]); free(DMX[1]); free(DPX[0]); free(DPX[1]); free(Dx); free(Dy);
+    }   /* omp parallel */
+    /* reductions in leaf order, then commit */
+    for (k = 0; k < s->n_leaves; ++k) {
+        if (act && !act[k]) continue;
+        if (leaf_smax[k] > smax_all) smax_all = leaf_smax[k];
+        s->bnd_mass += leaf_bnd[k];
+    }
+#pragma omp parallel for schedule(static)
     for (k = 0; k < s->n_leaves; ++k) {
         leaf_t *L = &s->leaves[k];
         int i, j, f;
@@ -1205,9 +1275,7 @@ static double update_all(orc_sim *s, double dt, const char *act)
             free(newq[3 * k + f]);
         }
     }
-    free(newq);
-    free(EX); free(EY); free(FX); free(GY); free(FXt); free(GYt);
-    free(DMX[0]); free(DMX[1]); free(DPX[0]); free(DPX[1]); free(Dx); free(Dy);
+    free(newq); free(leaf_smax); free(leaf_bnd);
     return smax_all;
 }
 
@@ -1217,7 +1285,7 @@ static double update_all(orc_sim *s, double dt, const char *act)
 
 /* Semi-implicit Manning sink on the new state of every wet cell:
  * (hu, hv) /= 1 + dt g n^2 |u| h^(-4/3), |u| h^(-4/3) = |hu| / (h h cbrt(h)). */
-static void friction_leaf(orc_sim *s, leaf_t *L, double dt)
+static void friction_leaf(const orc_sim *s, leaf_t *L, double dt)
 {
     int m = s->m, i, j;
     double n2 = s->manning * s->manning;
@@ -1235,19 +1303,39 @@ static void friction_leaf(orc_sim *s, leaf_t *L, double dt)
         }
 }
 
-static void clamp_leaf(orc_sim *s, leaf_t *L)
+/* Positivity (reading R13) on one leaf; returns the volume the leaf's clamp
+ * added (summed in cell order), which the caller adds to the budget in leaf
+ * order. */
+static double clamp_leaf(const orc_sim *s, leaf_t *L)
 {
     int m = s->m, i, j;
-    double area = DX(s, L->level) * DY(s, L->level);
+    double area = DX(s, L->level) * DY(s, L->level), added = 0.0;
     for (j = 0; j < m; ++j)
         for (i = 0; i < m; ++i) {
             int gi = G(s, i, j);
             if (L->q[0][gi] < 0.0) {
-                s->clamp_mass += (-L->q[0][gi]) * area;
+                added += (-L->q[0][gi]) * area;
                 L->q[0][gi] = 0.0;
             }
             if (!wet(s, L->q[0][gi])) { L->q[1][gi] = 0.0; L->q[2][gi] = 0.0; }
         }
+    return added;
+}
+
+/* Friction then positivity on the leaves marked in act (NULL: all), leaves
+ * in parallel; the clamp volume joins the budget in leaf order. */
+static void friction_clamp_sel(orc_sim *s, double dt, const char *act)
+{
+    int k;
+    double *added = (double *)calloc((size_t)s->n_leaves + 1, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < s->n_leaves; ++k) {
+        if (act && !act[k]) continue;
+        friction_leaf(s, &s->leaves[k], dt);
+        added[k] = clamp_leaf(s, &s->leaves[k]);
+    }
+    for (k = 0; k < s->n_leaves; ++k) s->clamp_mass += added[k];
+    free(added);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1263,9 +1351,14 @@ static void clamp_leaf(orc_sim *s, leaf_t *L)
    the fine leaves' records summed over their substeps, in place of gainF */
 static void reflux_sel(orc_sim *s, const char *lev, double *const *gacc)
 {
-    int m = s->m, k, f, kk, q;
+    int m = s->m, k;
+    double *added = (double *)calloc((size_t)s->n_leaves + 1, sizeof(double));
+    /* each coarse leaf corrects only its own cells from the fine leaves'
+       records, which nothing changes here: leaves in parallel */
+#pragma omp parallel for schedule(dynamic, 4)
     for (k = 0; k < s->n_leaves; ++k) {
         leaf_t *C = &s->leaves[k];
+        int f, kk, q;
         if (lev && !lev[C->level]) continue;
         long ni = NI(s, C->level), nj = NJ(s, C->level);
         double area = DX(s, C->level) * DY(s, C->level);
@@ -1319,8 +1412,10 @@ static void reflux_sel(orc_sim *s, const char *lev, double *const *gacc)
                 }
             }
         }
-        if (touched) clamp_leaf(s, C);
+        if (touched) added[k] = clamp_leaf(s, C);
     }
+    for (k = 0; k < s->n_leaves; ++k) s->clamp_mass += added[k];
+    free(added);
 }
 
 static void reflux_all(orc_sim *s) { reflux_sel(s, NULL, NULL); }
@@ -1334,16 +1429,20 @@ double orc_max_speed(orc_sim *s)
 {
     int m = s->m, k, ne = m + 3;
     double smax = 0.0;
-    edge_t *E = (edge_t *)malloc(sizeof(edge_t) * (size_t)(m + 2) * ne);
     orc_fill_ghosts(s);
-    for (k = 0; k < s->n_leaves; ++k) {
-        leaf_t *L = &s->leaves[k];
-        double a = sweep_solve(s, L, 0, E) / DX(s, L->level);
-        double b = sweep_solve(s, L, 1, E) / DY(s, L->level);
-        if (a > smax) smax = a;
-        if (b > smax) smax = b;
+#pragma omp parallel reduction(max : smax)
+    {
+        edge_t *E = (edge_t *)malloc(sizeof(edge_t) * (size_t)(m + 2) * ne);
+#pragma omp for schedule(dynamic, 4)
+        for (k = 0; k < s->n_leaves; ++k) {
+            leaf_t *L = &s->leaves[k];
+            double a = sweep_solve(s, L, 0, E) / DX(s, L->level);
+            double b = sweep_solve(s, L, 1, E) / DY(s, L->level);
+            if (a > smax) smax = a;
+            if (b > smax) smax = b;
+        }
+        free(E);
     }
-    free(E);
     return smax;
 }
 
@@ -1352,14 +1451,10 @@ double orc_max_speed(orc_sim *s)
  * Courant number is dt times it).  Does not advance the clock. */
 double orc_step(orc_sim *s, double dt)
 {
-    int k;
     double smax;
     orc_fill_ghosts_at(s, s->t);
     smax = update_all(s, dt, NULL);
-    for (k = 0; k < s->n_leaves; ++k) {
-        friction_leaf(s, &s->leaves[k], dt);
-        clamp_leaf(s, &s->leaves[k]);
-    }
+    friction_clamp_sel(s, dt, NULL);
     reflux_all(s);
     return smax;
 }
@@ -1453,10 +1548,9 @@ static double lts_macro(orc_sim *s, double dt, int L0, int L1, char *act, double
             if (!any) { free(al); continue; }
             sm = update_all(s, dtl, al);
             if (dtl * sm > nu) nu = dtl * sm;
+            friction_clamp_sel(s, dtl, al);
             for (k = 0; k < s->n_leaves; ++k) {
                 if (!al[k]) continue;
-                friction_leaf(s, &s->leaves[k], dtl);
-                clamp_leaf(s, &s->leaves[k]);
                 if (!half[l]) memcpy(gacc[k], s->leaves[k].gainF, sizeof(double) * 12 * (size_t)m);
                 else
                     for (f = 0; f < 12 * m; ++f) gacc[k][f] = gacc[k][f] + s->leaves[k].gainF[f];
@@ -1474,16 +1568,20 @@ static double lts_speed(orc_sim *s, int L0)
 {
     int m = s->m, k, ne = m + 3;
     double smax = 0.0;
-    edge_t *E = (edge_t *)malloc(sizeof(edge_t) * (size_t)(m + 2) * ne);
     orc_fill_ghosts(s);
-    for (k = 0; k < s->n_leaves; ++k) {
-        leaf_t *L = &s->leaves[k];
-        double a = sweep_solve(s, L, 0, E) / DX(s, L->level);
-        double b = sweep_solve(s, L, 1, E) / DY(s, L->level);
-        double v = (a > b ? a : b) / (double)(1 << (L->level - L0));
-        if (v > smax) smax = v;
+#pragma omp parallel reduction(max : smax)
+    {
+        edge_t *E = (edge_t *)malloc(sizeof(edge_t) * (size_t)(m + 2) * ne);
+#pragma omp for schedule(dynamic, 4)
+        for (k = 0; k < s->n_leaves; ++k) {
+            leaf_t *L = &s->leaves[k];
+            double a = sweep_solve(s, L, 0, E) / DX(s, L->level);
+            double b = sweep_solve(s, L, 1, E) / DY(s, L->level);
+            double v = (a > b ? a : b) / (double)(1 << (L->level - L0));
+            if (v > smax) smax = v;
+        }
+        free(E);
     }
-    free(E);
     return smax;
 }
 
@@ -1642,9 +1740,11 @@ static int grade_holds(const orc_sim *s, const leaf_t *L, int g)
    4. the scenario's level limits. */
 void orc_tag(const orc_sim *s, signed char *flags)
 {
-    int m = s->m, k, i, j, g, r;
+    int m = s->m, k;
+#pragma omp parallel for schedule(dynamic, 4)
     for (k = 0; k < s->n_leaves; ++k) {
         const leaf_t *L = &s->leaves[k];
+        int i, j, g, r;
         int ref = 0, keep = 0, f, target = -1, lo = -1, hi = -1;
         for (j = 0; j < m; ++j)
             for (i = 0; i < m; ++i) {

@@ -51,14 +51,18 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src, extra in UNITS:
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        out = _run(["hipcc", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
-        if verbose and out:
-            print(out)
-        objs.append(obj)
+    objs = [os.path.join(BUILD, os.path.splitext(src)[0] + ".o") for src, _ in UNITS]
+    cmds = [["hipcc", *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+            for (src, extra), obj in zip(UNITS, objs)]
+    # the units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        outs = list(ex.map(_run, cmds))
+    if verbose:
+        for out in outs:
+            if out:
+                print(out)
     tmp = LIB + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)
