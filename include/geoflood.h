@@ -50,6 +50,7 @@ enum {
 
 enum { GF_FP64 = 0, GF_FP32 = 1 };                     /* arithmetic of a context */
 enum { GF_BC_WALL = 0, GF_BC_EXTRAP = 1, GF_BC_INFLOW = 2 };
+enum { GF_TAG_PLAIN = 0, GF_TAG_LEARNED = 1 };         /* gf_tag modes */
 
 /* One independent scenario (an ensemble member).  Sides: 0 x-low, 1 x-high,
  * 2 y-low, 3 y-high. */
@@ -96,6 +97,8 @@ typedef struct {
     const gf_scenario_desc *scen;
     int64_t max_patches;         /* patch pool capacity over all scenarios */
     void *hip_stream;            /* hipStream_t or NULL */
+    const char *autotune_cache;  /* nullable: cache file gf_autotune uses when its own path is NULL;
+                                  * copied at gf_create */
 } gf_config;
 
 typedef struct {
@@ -104,6 +107,8 @@ typedef struct {
     int64_t cell_updates;        /* interior leaf cells x accepted steps */
     double t_min, t_max;         /* scenario times after the call */
     double dt_min, dt_max;       /* next step lengths after the call */
+    double cfl_max;              /* largest Courant number of the accepted steps of the call */
+    double seconds;              /* wall time of the call, the final synchronisation included */
 } gf_step_stats;
 
 /* Create a context: validates the configuration and allocates the patch
@@ -120,6 +125,27 @@ void gf_destroy(gf_ctx *ctx);
  * children.  Errors: GF_E_INVALID on shape mismatch. */
 int gf_set_bathymetry(gf_ctx *ctx, int32_t scen, const double *dem_nodes, int64_t nx, int64_t ny,
                       int32_t dem_level);
+
+/* Initial state from a host callback (the initial condition of an IVP on
+ * the quadtree, Section 4; Section 5.1 and 6.2 set theirs this way: a dry
+ * start, or a reservoir over the terrain).  For every leaf of scenario
+ * `scen`, in leaf order, the library calls
+ *   ic(user, scen, level, x0, y0, dx, dy, m, m, b, h, hu, hv)
+ * with (x0, y0) the leaf's lower-left corner, (dx, dy) its cell size, b its
+ * m*m interior bed values as the library holds them (FP32 contexts: the
+ * rounded bed, widened), and h, hu, hv m*m arrays (row-major, j outer) that
+ * the callback fills; the library then stores them (rounded to nearest even
+ * in an FP32 context).  Then, up to max_passes times: the plain criteria
+ * tag the scenario's leaves (other scenarios are left alone), the mesh is
+ * regridded with those flags, and the callback sets the new leaves again;
+ * a pass that changes no leaf ends the loop.  The callback runs on the
+ * calling thread and must not call into the library.  Clocks and budgets of
+ * the scenario restart at t = 0.
+ * Errors: GF_E_INVALID (null callback, max_passes < 0), GF_E_STATE (no
+ * bathymetry or leaves), GF_E_NOMEM (pool too small for a pass). */
+typedef void (*gf_ic_fn)(void *user, int32_t scen, int32_t level, double x0, double y0, double dx, double dy,
+                         int32_t nx, int32_t ny, const double *b, double *h, double *hu, double *hv);
+int gf_set_initial(gf_ctx *ctx, int32_t scen, gf_ic_fn ic, void *user, int32_t max_passes);
 
 /* Replace the mesh of a scenario by the given leaves (n rows of 4 int32, any
  * order; stored in leaf order).  The leaves must tile the domain and be 2:1
@@ -185,14 +211,18 @@ int gf_step_plain(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_s
 int gf_step_lts(gf_ctx *ctx, int32_t nsteps, const double *dt_fixed, gf_step_stats *out);
 
 /* Refinement flags of every leaf of every scenario, concatenated in scenario
- * then leaf order: +1 refine, -1 coarsen, 0 keep (Section 4.1).  In order:
- * the cell criteria (depth, free-surface gradient, advancing front, speed,
+ * then leaf order: +1 refine, -1 coarsen, 0 keep (Section 4.1).
+ * mode GF_TAG_PLAIN, the criteria of Section 4.1, in order: the cell
+ * criteria (depth, free-surface gradient, advancing front, speed,
  * velocity-depth product) refine at their thresholds and keep at half of
  * them, else the leaf coarsens; flow grades that hold set the leaf's level;
  * flood-source regions force or cap it; the scenario's level limits apply
- * last.  Decided in FP64 with * + - and compares only.  `flags_out` is
- * nullable (the flags are kept for gf_regrid). */
-int gf_tag(gf_ctx *ctx, int8_t *flags_out, int64_t cap, int64_t *n);
+ * last.  Decided in FP64 with * + - and compares only.
+ * mode GF_TAG_LEARNED: the network's flags, as gf_net_predict (needs
+ * parameters: GF_E_STATE otherwise).
+ * `flags_out` is nullable (the flags are kept for gf_regrid).
+ * Errors: GF_E_INVALID (mode, cap < leaf count), GF_E_STATE. */
+int gf_tag(gf_ctx *ctx, int32_t mode, int8_t *flags_out, int64_t cap, int64_t *n);
 
 /* Gauges: the time series at control points that Section 5.1 plots.  Point k
  * (scenario scen[k], x = xy[2k], y = xy[2k+1], inside its domain) reads the
@@ -235,7 +265,8 @@ int gf_get_step_threads(gf_ctx *ctx, int32_t *nt);
 /* Autotuner: time every built step-kernel shape (workgroup size x schedule)
  * for `steps` steps on the context's current state, keep the fastest, and
  * restore the state, clocks and budgets after each trial, so the simulation
- * is unchanged.  cache_path (nullable): a text file of earlier choices keyed
+ * is unchanged.  cache_path (nullable; NULL takes gf_config.autotune_cache,
+ * which may be NULL too): a text file of earlier choices keyed
  * by GPU architecture, precision, patch size and patch count (rounded up to a
  * power of two); a hit skips the timing (us_per_step is then -1), a miss
  * appends the new choice.  Outputs are nullable.
@@ -302,6 +333,18 @@ int gf_net_forward(gf_ctx *ctx, const double *x, int32_t n, double *logits);
  * beta2 0.999, eps 1e-8).  Errors: GF_E_STATE (no parameters), GF_E_INVALID. */
 int gf_net_train_step(gf_ctx *ctx, const double *x, const int8_t *y, int32_t n, const double *class_w, double lr,
                       double *loss, double *grad);
+/* The same training step on a batch already in device memory (a caller's
+ * torch tensors): x_bf16 n x GF_NET_FEATURES bfloat16 values (uint16 bit
+ * patterns, [sample][y][x][channel]), y n int8 labels.  Both must stay valid
+ * until the context stream has run the step; nothing is copied to the host
+ * unless loss is requested (then the stream is synchronised).  The class
+ * weight sum of the batch is formed on the device; a label outside 0..2
+ * counts with weight 0 (no loss, no gradient).  A batch whose weights sum to
+ * zero leaves the parameters unchanged and gives loss 0.
+ * Errors: GF_E_INVALID (null pointers, n <= 0, lr < 0), GF_E_STATE (no
+ * parameters), GF_E_NOMEM, GF_E_HIP. */
+int gf_net_train_step_dev(gf_ctx *ctx, const uint16_t *x_bf16, const int8_t *y, int32_t n, const double *class_w,
+                          double lr, double *loss);
 /* Flags from the network for every leaf (largest logit, kept within each
  * scenario's level limits), in leaf order; they become the flags that
  * gf_regrid(ctx, NULL, ...) applies, as after gf_tag. */

@@ -35,12 +35,14 @@ class gf_scenario_desc(C.Structure):
 class gf_config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("m", C.c_int32), ("g", C.c_double), ("dry_tol", C.c_double),
                 ("cfl_desired", C.c_double), ("cfl_max", C.c_double), ("n_scen", C.c_int32),
-                ("scen", C.POINTER(gf_scenario_desc)), ("max_patches", C.c_int64), ("hip_stream", C.c_void_p)]
+                ("scen", C.POINTER(gf_scenario_desc)), ("max_patches", C.c_int64), ("hip_stream", C.c_void_p),
+                ("autotune_cache", C.c_char_p)]
 
 
 class gf_step_stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("rejected", C.c_int64), ("cell_updates", C.c_int64),
-                ("t_min", C.c_double), ("t_max", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double)]
+                ("t_min", C.c_double), ("t_max", C.c_double), ("dt_min", C.c_double), ("dt_max", C.c_double),
+                ("cfl_max", C.c_double), ("seconds", C.c_double)]
 
 
 class gf_run_stats(C.Structure):
@@ -49,14 +51,20 @@ class gf_run_stats(C.Structure):
 
 
 GF_RUN_PLAIN, GF_RUN_SPARSE, GF_RUN_LEARNED = 0, 1, 2
+GF_TAG_PLAIN, GF_TAG_LEARNED = 0, 1
+
+# void ic(user, scen, level, x0, y0, dx, dy, nx, ny, const double *b, double *h, double *hu, double *hv)
+GF_IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                       C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                       C.POINTER(C.c_double))
 NET_PARAMS = 14579
 NET_FEATURES = 2304
 
-EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
+EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_initial", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain", "gf_step_lts",
            "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
            "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
-           "gf_net_forward", "gf_net_train_step", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
+           "gf_net_forward", "gf_net_train_step", "gf_net_train_step_dev", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
 
 _lib = None
 
@@ -93,7 +101,8 @@ def load(path: str = LIB_PATH):
     L.gf_step.argtypes = [vp, i32, dp, C.POINTER(gf_step_stats)]
     L.gf_step_plain.argtypes = [vp, i32, dp, C.POINTER(gf_step_stats)]
     L.gf_step_lts.argtypes = [vp, i32, dp, C.POINTER(gf_step_stats)]
-    L.gf_tag.argtypes = [vp, C.POINTER(C.c_int8), i64, C.POINTER(i64)]
+    L.gf_tag.argtypes = [vp, i32, C.POINTER(C.c_int8), i64, C.POINTER(i64)]
+    L.gf_set_initial.argtypes = [vp, i32, GF_IC_FN, vp, i32]
     L.gf_regrid.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(i64)]
     L.gf_mass.argtypes = [vp, i32, dp, dp, dp]
     L.gf_time.argtypes = [vp, i32, dp, dp, C.POINTER(i64), C.POINTER(i64)]
@@ -111,6 +120,7 @@ def load(path: str = LIB_PATH):
     L.gf_net_features.argtypes = [vp, dp, i64, C.POINTER(i64)]
     L.gf_net_forward.argtypes = [vp, dp, i32, dp]
     L.gf_net_train_step.argtypes = [vp, dp, i8p, i32, dp, C.c_double, dp, dp]
+    L.gf_net_train_step_dev.argtypes = [vp, vp, vp, i32, dp, C.c_double, dp]
     L.gf_net_predict.argtypes = [vp, i8p, i64, C.POINTER(i64)]
     L.gf_net_collect.argtypes = [vp, i32, i32, dp, i8p, i64, C.POINTER(i64)]
     L.gf_run.argtypes = [vp, i32, i32, i32, i32, C.POINTER(gf_run_stats)]
@@ -149,7 +159,7 @@ class Context:
 
     def __init__(self, scenarios: Sequence, precision: int = GF_FP64, max_patches: Optional[int] = None,
                  g: float = 9.81, dry_tol: float = 1e-4, cfl_desired: float = 0.9, cfl_max: float = 1.0,
-                 stream=None):
+                 stream=None, autotune_cache: Optional[str] = None):
         L = load()
         self.L = L
         self.scenarios = list(scenarios)
@@ -184,7 +194,8 @@ class Context:
             max_patches = int(min(max_patches, 200000))
         cfg = gf_config(precision=precision, m=self.m, g=g, dry_tol=dry_tol, cfl_desired=cfl_desired,
                         cfl_max=cfl_max, n_scen=len(self.scenarios), scen=descs, max_patches=max_patches,
-                        hip_stream=stream if stream is not None else _stream_handle())
+                        hip_stream=stream if stream is not None else _stream_handle(),
+                        autotune_cache=autotune_cache.encode() if autotune_cache else None)
         self._p = C.c_void_p()
         rc = L.gf_create(C.byref(cfg), C.byref(self._p))
         if rc != 0:
@@ -268,12 +279,13 @@ class Context:
             self._chk(fn(self._p, nsteps, None, C.byref(st)))
         return st
 
-    def tag(self) -> np.ndarray:
+    def tag(self, mode: int = GF_TAG_PLAIN) -> np.ndarray:
+        """Flags of every leaf: the plain criteria (GF_TAG_PLAIN) or the network (GF_TAG_LEARNED)."""
         n = C.c_int64()
-        self._chk(self.L.gf_tag(self._p, None, 0, C.byref(n)))
-        out = np.zeros(n.value, dtype=np.int8)
-        self._chk(self.L.gf_tag(self._p, out.ctypes.data_as(C.POINTER(C.c_int8)), n.value, C.byref(n)))
-        return out
+        cap = sum(self.leaves(k).shape[0] for k in range(len(self.scenarios)))
+        out = np.zeros(max(cap, 1), dtype=np.int8)
+        self._chk(self.L.gf_tag(self._p, mode, out.ctypes.data_as(C.POINTER(C.c_int8)), cap, C.byref(n)))
+        return out[:n.value].copy()
 
     def set_gauges(self, points, cap: int = 4096):
         """Gauges at points [(scenario, x, y)], up to cap records each."""
@@ -379,6 +391,23 @@ class Context:
                                            _dptr(cw), lr, C.byref(loss), _dptr(g) if want_grad else None))
         return (loss.value, g) if want_grad else loss.value
 
+    def net_train_step_dev(self, x_bf16, y, class_w, lr: float, want_loss: bool = True):
+        """One training step on a batch in device memory: x_bf16 a torch int16 /
+        uint16 / bfloat16 tensor of n x 2304 values, y a torch int8 tensor of n
+        labels, both on the context's device."""
+        n = int(y.numel())
+        if x_bf16.numel() != n * NET_FEATURES:
+            raise ValueError("x_bf16 needs n x 2304 values")
+        if not (x_bf16.is_contiguous() and y.is_contiguous()):
+            raise ValueError("x_bf16 and y must be contiguous")
+        if x_bf16.element_size() != 2 or y.element_size() != 1:
+            raise ValueError("x_bf16 holds 16-bit values and y 8-bit labels")
+        cw = np.ascontiguousarray(class_w, dtype=np.float64)
+        loss = C.c_double()
+        self._chk(self.L.gf_net_train_step_dev(self._p, C.c_void_p(x_bf16.data_ptr()), C.c_void_p(y.data_ptr()), n,
+                                               _dptr(cw), lr, C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
     def net_predict(self) -> np.ndarray:
         n = C.c_int64()
         cap = sum(self.leaves(k).shape[0] for k in range(len(self.scenarios)))
@@ -408,16 +437,35 @@ class Context:
         return a.value, b.value
 
     # ------------------------------------------------------------ helpers
-    def set_initial(self, scen: int = 0, precision: Optional[str] = None):
-        """Initial state from the scenario recipe, formed from this library's own bathymetry."""
+    def set_initial_fn(self, scen: int, fn, max_passes: int = 0):
+        """gf_set_initial with a Python callback fn(level, x0, y0, dx, dy, b) ->
+        (h, hu, hv), b and the results m x m arrays [j][i]."""
+        m = self.m
+
+        def ic(user, s, level, x0, y0, dx, dy, nx, ny, b, h, hu, hv):
+            bb = np.ctypeslib.as_array(b, shape=(ny, nx)).copy()
+            H, HU, HV = fn(level, x0, y0, dx, dy, bb)
+            for ptr, v in ((h, H), (hu, HU), (hv, HV)):
+                np.ctypeslib.as_array(ptr, shape=(ny, nx))[:] = np.asarray(v, dtype=np.float64).reshape(ny, nx)
+        cb = GF_IC_FN(ic)
+        self._chk(self.L.gf_set_initial(self._p, scen, cb, None, int(max_passes)))
+
+    def set_initial(self, scen: int = 0, precision: Optional[str] = None, max_passes: int = 0):
+        """Initial state from the scenario recipe (inputs.initial_state, formed
+        from this library's own bed) through gf_set_initial; max_passes rounds
+        of plain tagging and regridding around it.  Returns the state."""
         from .inputs import initial_state
         if precision is None:
             precision = "f32" if self.precision == GF_FP32 else "f64"
         sc = self.scenarios[scen]
-        lv = self.leaves(scen)
-        st = self.state(scen)
-        for k in range(lv.shape[0]):
-            h, hu, hv = initial_state(sc, lv[k], st[k, 3], precision)
-            st[k, 0], st[k, 1], st[k, 2] = h, hu, hv
-        self.set_state(scen, st)
-        return st
+        m = self.m
+
+        def fn(level, x0, y0, dx, dy, b):
+            # the leaf (tree, level, ix, iy) from its corner
+            PI = int(round((x0 - sc.x0) / (dx * m)))
+            PJ = int(round((y0 - sc.y0) / (dy * m)))
+            n = 1 << level
+            leaf = ((PJ // n) * sc.mi + PI // n, level, PI % n, PJ % n)
+            return initial_state(sc, leaf, b, precision)
+        self.set_initial_fn(scen, fn, max_passes)
+        return self.state(scen)

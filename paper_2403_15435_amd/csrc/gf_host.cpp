@@ -202,6 +202,7 @@ struct gf_ctx {
     // gauges: points, their cells on the current mesh, device records
     struct GaugePoint { int32_t scen; double x, y; };
     std::vector<GaugePoint> gauges;
+    std::string tune_cache;          // gf_config.autotune_cache, copied
     GaugeDev *d_gauges = nullptr;
     double *d_grec = nullptr;
     int64_t *d_gcount = nullptr;
@@ -239,6 +240,7 @@ struct gf_ctx {
         float *x = nullptr;                 // staged features [rows][FEAT]
         int8_t *y = nullptr;
         float *logits = nullptr, *loss = nullptr, *part = nullptr;
+        float *wtot = nullptr;              // class-weight sum of a device batch
         int64_t n_cap = 0;
         float *featf = nullptr;
         uint16_t *featb = nullptr;
@@ -1040,6 +1042,7 @@ int plain_attempt(gf_ctx *c, const std::vector<PlainGroup> &groups, double dt_fi
         D.steps += 1;
         D.cur ^= 1;
         D.accepted_last = 1;
+        D.nu_max = std::max(D.nu_max, nu);
         any_accepted = true;
         if (!fixed) D.dt = nu > 0.0 ? dtu * c->cfg.cfl_desired / nu : dtu;
     }
@@ -1193,6 +1196,8 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     gf_ctx *c = new gf_ctx();
     c->cfg = *cfg;
     c->cfg.scen = nullptr;
+    if (cfg->autotune_cache) c->tune_cache = cfg->autotune_cache;
+    c->cfg.autotune_cache = nullptr;
     c->prec = cfg->precision;
     c->m = cfg->m;
     c->step_threads = cfg->m == 16 ? 64 : 256;
@@ -1227,7 +1232,7 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     const size_t MM = (size_t)c->m * c->m;
     auto alloc = [&](void **p, size_t bytes) -> bool {
         hipError_t e = hipMalloc(p, bytes);
-        if (e == hipSuccess) e = hipMemset(*p, 0, bytes);
+        if (e == hipSuccess) e = hipMemsetAsync(*p, 0, bytes, c->stream);
         if (e != hipSuccess) {
             snprintf(g_create_err, sizeof g_create_err, "allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
             return false;
@@ -1252,8 +1257,9 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     }
     std::vector<TagRules> rules;
     for (auto &s : c->sc) rules.push_back(s.rules);
-    if (hipMemcpy(c->d_rules, rules.data(), sizeof(TagRules) * rules.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        push_scen(c) != GF_OK) {
+    if (hipMemcpyAsync(c->d_rules, rules.data(), sizeof(TagRules) * rules.size(), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        push_scen(c) != GF_OK || hipStreamSynchronize(c->stream) != hipSuccess) {
         gf_destroy(c);
         return GF_E_HIP;
     }
@@ -1275,7 +1281,8 @@ void gf_destroy(gf_ctx *c)
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
-                  c->net.part, c->net.featf, c->net.featb, c->net.img, c->net.map, c->net.lv, c->net.lij};
+                  c->net.part, c->net.featf, c->net.featb, c->net.img, c->net.map, c->net.lv, c->net.lij,
+                  c->net.wtot};
     for (void *p : pn)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1494,21 +1501,24 @@ int gf_get_ghosted(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, double 
 
 namespace {
 // statistics of a gf_step / gf_step_plain call and its status
-int step_result(gf_ctx *c, const std::vector<int64_t> &steps0, const std::vector<int64_t> &rej0, gf_step_stats *out)
+int step_result(gf_ctx *c, const std::vector<int64_t> &steps0, const std::vector<int64_t> &rej0, gf_step_stats *out,
+                std::chrono::steady_clock::time_point t0, const std::vector<int64_t> *work = nullptr)
 {
     int status = GF_OK;
     gf_step_stats st{};
     st.t_min = 1e300; st.t_max = -1e300; st.dt_min = 1e300; st.dt_max = -1e300;
     for (size_t i = 0; i < c->hs.size(); ++i) {
         const ScenDev &h = c->hs[i];
+        st.cfl_max = std::max(st.cfl_max, h.nu_max);
         if (h.status != 0 && status == GF_OK) status = h.status;
         st.steps += h.steps - steps0[i];
         st.rejected += h.rejected - rej0[i];
-        const int64_t cells = (int64_t)c->sc[i].leaves.size() * c->m * c->m;
+        const int64_t cells = work ? (*work)[i] : (int64_t)c->sc[i].leaves.size() * c->m * c->m;
         st.cell_updates += (h.steps - steps0[i]) * cells;
         st.t_min = std::min(st.t_min, h.t); st.t_max = std::max(st.t_max, h.t);
         st.dt_min = std::min(st.dt_min, h.dt); st.dt_max = std::max(st.dt_max, h.dt);
     }
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (out) *out = st;
     if (status == -5) return fail(c, GF_E_CFL, "a fixed step exceeded the maximum Courant number");
     if (status == -6) return fail(c, GF_E_NUMERIC, "non-finite state produced");
@@ -1518,6 +1528,7 @@ int step_result(gf_ctx *c, const std::vector<int64_t> &steps0, const std::vector
 
 int gf_step(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *out)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     if (!c) return GF_E_INVALID;
     if (nsteps < 0) return fail(c, GF_E_INVALID, "negative step count");
     for (auto &s : c->sc)
@@ -1528,6 +1539,7 @@ int gf_step(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *ou
     for (size_t i = 0; i < c->hs.size(); ++i) {
         ScenDev &h = c->hs[i];
         h.status = 0;
+        h.nu_max = 0.0;
         h.target = h.steps + nsteps;
         steps0[i] = h.steps;
         rej0[i] = h.rejected;
@@ -1563,11 +1575,12 @@ int gf_step(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *ou
             if (rc) return rc;
         }
     }
-    return step_result(c, steps0, rej0, out);
+    return step_result(c, steps0, rej0, out, t0);
 }
 
 int gf_step_plain(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *out)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     if (!c) return GF_E_INVALID;
     if (nsteps < 0) return fail(c, GF_E_INVALID, "negative step count");
     for (auto &s : c->sc)
@@ -1581,6 +1594,7 @@ int gf_step_plain(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_sta
     for (size_t i = 0; i < c->hs.size(); ++i) {
         ScenDev &h = c->hs[i];
         h.status = 0;
+        h.nu_max = 0.0;
         h.target = h.steps + nsteps;
         steps0[i] = h.steps;
         rej0[i] = h.rejected;
@@ -1612,11 +1626,12 @@ int gf_step_plain(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_sta
             }
         }
     }
-    return step_result(c, steps0, rej0, out);
+    return step_result(c, steps0, rej0, out, t0);
 }
 
 int gf_step_lts(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats *out)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     if (!c) return GF_E_INVALID;
     if (nsteps < 0) return fail(c, GF_E_INVALID, "negative step count");
     for (auto &s : c->sc)
@@ -1643,6 +1658,7 @@ int gf_step_lts(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats
         for (const Leaf &L : s.leaves) work[i] += ((int64_t)c->m * c->m) << (L.level - L0);
         kmax = std::max(kmax, 1 << (L1 - L0));
         h.status = 0;
+        h.nu_max = 0.0;
         h.target = h.steps + nsteps;
         steps0[i] = h.steps;
         rej0[i] = h.rejected;
@@ -1701,27 +1717,14 @@ int gf_step_lts(gf_ctx *c, int32_t nsteps, const double *dt_fixed, gf_step_stats
     if (!rc) rc = pull_scen(c);
     c->flags_dirty = true;
     if (rc) return rc;
-    int status = GF_OK;
-    gf_step_stats st{};
-    st.t_min = 1e300; st.t_max = -1e300; st.dt_min = 1e300; st.dt_max = -1e300;
-    for (size_t i = 0; i < c->hs.size(); ++i) {
-        const ScenDev &h = c->hs[i];
-        if (h.status != 0 && status == GF_OK) status = h.status;
-        st.steps += h.steps - steps0[i];
-        st.rejected += h.rejected - rej0[i];
-        st.cell_updates += (h.steps - steps0[i]) * work[i];
-        st.t_min = std::min(st.t_min, h.t); st.t_max = std::max(st.t_max, h.t);
-        st.dt_min = std::min(st.dt_min, h.dt); st.dt_max = std::max(st.dt_max, h.dt);
-    }
-    if (out) *out = st;
-    if (status == -5) return fail(c, GF_E_CFL, "a fixed step exceeded the maximum Courant number");
-    if (status == -6) return fail(c, GF_E_NUMERIC, "non-finite state produced");
-    return status;
+    return step_result(c, steps0, rej0, out, t0, &work);
 }
 
-int gf_tag(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n)
+int gf_tag(gf_ctx *c, int32_t mode, int8_t *flags_out, int64_t cap, int64_t *n)
 {
     if (!c) return GF_E_INVALID;
+    if (mode == GF_TAG_LEARNED) return gf_net_predict(c, flags_out, cap, n);
+    if (mode != GF_TAG_PLAIN) return fail(c, GF_E_INVALID, "unknown tagging mode %d", mode);
     int rc = ensure_work(c);
     if (rc) return rc;
     const int nw = (int)c->desc.size();
@@ -2062,7 +2065,8 @@ int gf_net_set_params(gf_ctx *c, const double *params, int64_t n)
         size_t b = sizeof(float) * gfnet::N_PARAMS;
         if (hipMalloc((void **)&N.w, b) != hipSuccess || hipMalloc((void **)&N.m, b) != hipSuccess ||
             hipMalloc((void **)&N.v, b) != hipSuccess || hipMalloc((void **)&N.g, b) != hipSuccess ||
-            hipMalloc((void **)&N.wb, sizeof(uint16_t) * gfnet::N_PARAMS) != hipSuccess)
+            hipMalloc((void **)&N.wb, sizeof(uint16_t) * gfnet::N_PARAMS) != hipSuccess ||
+            hipMalloc((void **)&N.wtot, 64) != hipSuccess)
             return fail(c, GF_E_NOMEM, "network parameters");
     }
     std::vector<float> w((size_t)n);
@@ -2171,6 +2175,41 @@ int gf_net_train_step(gf_ctx *c, const double *x, const int8_t *y, int32_t n, co
     return GF_OK;
 }
 
+int gf_net_train_step_dev(gf_ctx *c, const uint16_t *x_bf16, const int8_t *y, int32_t n, const double *class_w,
+                          double lr, double *loss)
+{
+    if (!c) return GF_E_INVALID;
+    if (!x_bf16 || !y || !class_w || n <= 0 || !(lr >= 0.0))
+        return fail(c, GF_E_INVALID, "null batch pointer, empty batch or negative learning rate");
+    int rc = net_ready(c);
+    if (rc) return rc;
+    rc = net_stage_batch(c, nullptr, n);
+    if (rc) return rc;
+    auto &N = c->net;
+    hipError_t e = gfnet_launch_weight_sum(y, n, (float)class_w[0], (float)class_w[1], (float)class_w[2], N.wtot,
+                                           c->stream);
+    gfnet::NetArgs a{};
+    a.x = nullptr; a.xb = x_bf16; a.n = n; a.w = N.w; a.wb = N.wb; a.logits = N.logits;
+    a.y = y; a.cw[0] = (float)class_w[0]; a.cw[1] = (float)class_w[1]; a.cw[2] = (float)class_w[2];
+    a.wtot = 0.f; a.wtot_dev = N.wtot; a.loss_i = N.loss; a.part = N.part;
+    if (e == hipSuccess) e = gfnet_launch_train(a, c->stream);
+    if (e == hipSuccess) e = gfnet_launch_reduce(N.part, n, N.g, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "training launch: %s", hipGetErrorString(e));
+    N.t += 1;
+    const double bc1 = 1.0 - std::pow(0.9, (double)N.t), bc2 = 1.0 - std::pow(0.999, (double)N.t);
+    e = gfnet_launch_adam(N.w, N.m, N.v, N.wb, N.g, (float)lr, (float)bc1, (float)bc2, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "optimiser launch: %s", hipGetErrorString(e));
+    if (loss) {
+        std::vector<float> li((size_t)n);
+        HIPCHK(c, hipMemcpyAsync(li.data(), N.loss, sizeof(float) * li.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double L = 0.0;
+        for (float v : li) L += v;
+        *loss = L;
+    }
+    return GF_OK;
+}
+
 int gf_net_predict(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n_out)
 {
     if (!c) return GF_E_INVALID;
@@ -2237,7 +2276,7 @@ int gf_net_collect(gf_ctx *c, int32_t window, int32_t check_every, double *featu
         rc = gf_step(c, check_every, nullptr, nullptr);
         if (rc) return rc;
         int64_t nn = 0;
-        rc = gf_tag(c, fl.data(), n, &nn);
+        rc = gf_tag(c, GF_TAG_PLAIN, fl.data(), n, &nn);
         if (rc) return rc;
         if (nn != n) return fail(c, GF_E_STATE, "leaf set changed during a collection window");
         for (int64_t i = 0; i < n; ++i) {
@@ -2275,7 +2314,7 @@ int gf_run(gf_ctx *c, int32_t nsteps, int32_t mode, int32_t check_every, int32_t
         const bool regrid_step = mode == GF_RUN_PLAIN || k % regrid_every == 0;
         int64_t n = n_leaves(), nn = 0;
         plain.resize((size_t)n);
-        rc = gf_tag(c, plain.data(), n, &nn);
+        rc = gf_tag(c, GF_TAG_PLAIN, plain.data(), n, &nn);
         if (rc) break;
         if (regrid_step) {
             if (mode == GF_RUN_LEARNED) {
@@ -2351,6 +2390,63 @@ int gf_mass(gf_ctx *c, int32_t scen, double *mass, double *clamp_volume, double 
     if (clamp_volume) *clamp_volume = cl;
     if (boundary_volume) *boundary_volume = bd;
     return GF_OK;
+}
+
+int gf_set_initial(gf_ctx *c, int32_t scen, gf_ic_fn ic, void *user, int32_t max_passes)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    if (!ic || max_passes < 0) return fail(c, GF_E_INVALID, "null initial-condition callback or negative pass count");
+    Scen &S = c->sc[(size_t)scen];
+    if (!scen_ready(S)) return fail(c, GF_E_STATE, "scenario without bathymetry or leaves");
+    const int m = c->m;
+    const size_t MM = (size_t)m * m;
+    for (int pass = 0;; ++pass) {
+        const size_t n = S.leaves.size();
+        std::vector<double> st(n * 4 * MM), in(n * 3 * MM);
+        rc = gf_get_state(c, scen, st.data());
+        if (rc) return rc;
+        for (size_t k = 0; k < n; ++k) {
+            const Leaf &L = S.leaves[k];
+            const double dx = (S.d.x1 - S.d.x0) / (double)(((int64_t)S.d.mi * m) << L.level);
+            const double dy = (S.d.y1 - S.d.y0) / (double)(((int64_t)S.d.mj * m) << L.level);
+            const double x0 = S.d.x0 + (double)(L.PI * m) * dx, y0 = S.d.y0 + (double)(L.PJ * m) * dy;
+            ic(user, scen, L.level, x0, y0, dx, dy, m, m, &st[(k * 4 + 3) * MM], &in[(k * 3) * MM],
+               &in[(k * 3 + 1) * MM], &in[(k * 3 + 2) * MM]);
+        }
+        rc = gf_set_state(c, scen, in.data());
+        if (rc) return rc;
+        if (pass >= max_passes) break;
+        // the plain criteria on this scenario's leaves only
+        int64_t nall = 0, off = 0;
+        for (int32_t k = 0; k < scen; ++k) off += (int64_t)c->sc[(size_t)k].leaves.size();
+        for (auto &s2 : c->sc) nall += (int64_t)s2.leaves.size();
+        std::vector<int8_t> fl((size_t)nall);
+        int64_t nn = 0;
+        rc = gf_tag(c, GF_TAG_PLAIN, fl.data(), nall, &nn);
+        if (rc) return rc;
+        bool any = false;
+        for (int64_t k = 0; k < nall; ++k) {
+            if (k < off || k >= off + (int64_t)n) fl[(size_t)k] = 0;
+            any = any || fl[(size_t)k] != 0;
+        }
+        if (!any) break;
+        std::vector<uint64_t> before;
+        for (const Leaf &L : S.leaves) before.push_back(key_of(L.level, L.PI, L.PJ));
+        rc = gf_regrid(c, fl.data(), &nn);
+        if (rc) return rc;
+        std::vector<uint64_t> after;
+        for (const Leaf &L : S.leaves) after.push_back(key_of(L.level, L.PI, L.PJ));
+        if (after == before) break;
+    }
+    // the run starts here: clock, step count and budgets
+    rc = fold_accumulators(c);
+    if (rc) return rc;
+    S.clamp_base = 0.0;
+    S.bnd_base = 0.0;
+    ScenDev &h = c->hs[(size_t)scen];
+    h.t = 0.0; h.dt = 0.0; h.steps = 0; h.rejected = 0; h.status = 0; h.nu_max = 0.0;
+    return push_scen(c);
 }
 
 int gf_time(gf_ctx *c, int32_t scen, double *t, double *dt_next, int64_t *steps, int64_t *rejected)
@@ -2488,6 +2584,7 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
     int rc = ensure_work(c);
     if (rc) return rc;
     const TuneKey key = tune_key(c);
+    if (!cache_path && !c->tune_cache.empty()) cache_path = c->tune_cache.c_str();
     int best_nt = c->step_threads, best_sched = c->sched_wg;
     double best_us = -1.0;
     if (cache_lookup(cache_path, key.text, &best_nt, &best_sched)) {

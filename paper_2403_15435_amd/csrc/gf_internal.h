@@ -50,6 +50,7 @@ struct ScenDev {
     double t, dt, t_end;
     double dt_used;          // step length of the last attempt
     double nu_last;
+    double nu_max;           // largest Courant number of the accepted steps since the host reset it
     double manning_n;
     double inflow_lo, inflow_hi;
     double x0, y0;           // domain origin (cell centres x0 + (I + 1/2) dx)

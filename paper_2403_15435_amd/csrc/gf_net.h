@@ -24,6 +24,7 @@ struct NetArgs {
     const int8_t *y;         // class 0 (coarsen), 1 (keep), 2 (refine)
     float cw[3];             // class weights
     float wtot;              // sum over the batch of cw[y]
+    const float *wtot_dev;   // the same sum in device memory, used when not null
     float *loss_i;           // [n] per-sample loss contributions
     float *part;             // [n][N_PARAMS] per-sample gradients
 };
@@ -41,6 +42,9 @@ struct FeatLevel {
 hipError_t gfnet_launch_forward(const gfnet::NetArgs &a, hipStream_t s);
 hipError_t gfnet_launch_train(const gfnet::NetArgs &a, hipStream_t s);
 hipError_t gfnet_launch_reduce(const float *part, int n, float *grad, hipStream_t s);
+// class-weight sum of a batch whose labels are in device memory (labels
+// outside 0..2 count 0)
+hipError_t gfnet_launch_weight_sum(const int8_t *y, int n, float c0, float c1, float c2, float *wtot, hipStream_t s);
 hipError_t gfnet_launch_adam(float *w, float *m, float *v, uint16_t *wb, const float *g, float lr, float bc1, float bc2,
                              hipStream_t s);
 hipError_t gfnet_launch_to_bf16(const float *w, uint16_t *wb, int n, hipStream_t s);

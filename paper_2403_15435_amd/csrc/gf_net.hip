@@ -153,10 +153,16 @@ __global__ void __launch_bounds__(NT) net_kernel(const NetArgs a)
         const float zm = fmaxf(fmaxf(S.Z[0], S.Z[1]), S.Z[2]);
         float e[3], es = 0.f;
         for (int j = 0; j < 3; ++j) { e[j] = expf(S.Z[j] - zm); es += e[j]; }
-        const int y = a.y[s];
-        const float wy = a.cw[y];
-        a.loss_i[s] = wy * -logf(e[y] / es) / a.wtot;
-        for (int j = 0; j < 3; ++j) S.dZ[j] = (wy / a.wtot) * (e[j] / es - (j == y ? 1.f : 0.f));
+        // a label outside 0..2 (possible only for batches given in device
+        // memory) weighs 0; so does every sample of a batch whose weights sum to 0
+        const int yl = a.y[s];
+        const bool valid = yl >= 0 && yl <= 2;
+        const int y = valid ? yl : 1;
+        const float wt = a.wtot_dev ? *a.wtot_dev : a.wtot;
+        const float wy = valid && wt > 0.f ? a.cw[y] : 0.f;
+        const float den = wt > 0.f ? wt : 1.f;
+        a.loss_i[s] = wy * -logf(e[y] / es) / den;
+        for (int j = 0; j < 3; ++j) S.dZ[j] = (wy / den) * (e[j] / es - (j == y ? 1.f : 0.f));
     }
     __syncthreads();
     float *g = a.part + (int64_t)s * N_PARAMS;
@@ -424,9 +430,35 @@ hipError_t gfnet_launch_train(const NetArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// one workgroup: per-lane sums in label order, then a fixed tree
+__global__ void __launch_bounds__(256) weight_sum_kernel(const int8_t *y, int n, float c0, float c1, float c2,
+                                                         float *wtot)
+{
+    __shared__ float part[256];
+    const int tid = threadIdx.x;
+    float acc = 0.f;
+    for (int i = tid; i < n; i += 256) {
+        const int l = y[i];
+        acc += l == 0 ? c0 : (l == 1 ? c1 : (l == 2 ? c2 : 0.f));
+    }
+    part[tid] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) part[tid] += part[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) *wtot = part[0];
+}
+
 hipError_t gfnet_launch_reduce(const float *part, int n, float *grad, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_kernel, dim3((N_PARAMS + 255) / 256), dim3(256), 0, s, part, n, grad);
+    return hipGetLastError();
+}
+
+hipError_t gfnet_launch_weight_sum(const int8_t *y, int n, float c0, float c1, float c2, float *wtot, hipStream_t s)
+{
+    hipLaunchKernelGGL(weight_sum_kernel, dim3(1), dim3(256), 0, s, y, n, c0, c1, c2, wtot);
     return hipGetLastError();
 }
 

@@ -45,6 +45,34 @@ def test_version_and_null_context():
     assert L.gf_set_gauges(None, 0, None, None, 1) == gf.GF_E_INVALID
     assert L.gf_step_lts(None, 1, None, None) == gf.GF_E_INVALID
     assert L.gf_get_gauges(None, 0, None, 0, None) == gf.GF_E_INVALID
+    assert L.gf_tag(None, gf.GF_TAG_PLAIN, None, 0, None) == gf.GF_E_INVALID
+    assert L.gf_set_initial(None, 0, gf.GF_IC_FN(0), None, 0) == gf.GF_E_INVALID
+    assert L.gf_net_train_step_dev(None, None, None, 1, None, 0.1, None) == gf.GF_E_INVALID
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets the C
+    compiler gives the header's structures."""
+    import subprocess
+    import paper_2403_15435_amd as gf
+    structs = {"gf_config": gf.gf_config, "gf_step_stats": gf.gf_step_stats, "gf_run_stats": gf.gf_run_stats,
+               "gf_scenario_desc": gf.gf_scenario_desc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "geoflood.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
 
 
 @pytest.mark.parametrize("bad", ["u", "q", "n_regions", "region_box", "region_levels", "region_fraction",

@@ -1,0 +1,150 @@
+"""The entry points of the boundary beyond stepping: the initial condition
+from a host callback with refinement passes, the Courant number and wall time
+a step call reports, tagging by mode, and network training on a batch held in
+device memory.  Compared with the CPU oracle where it defines the result, and
+bit for bit with the host-array entry points that compute the same thing."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2403_15435_amd as gf
+from paper_2403_15435_amd import inputs
+from helpers import init_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _amr_reservoir():
+    sc = inputs.reservoir_fractal(level=3, m=16, radius=300.0, L=2000.0, seed=2)
+    sc.min_level, sc.max_level, sc.init_level = 1, 4, 1
+    return sc
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_set_initial_with_refinement_passes_matches_oracle(orc, prec):
+    """gf_set_initial: the recipe on every leaf, then passes of plain tagging,
+    regridding and the recipe again.  The oracle takes the same passes by
+    hand; leaves and state must agree bit for bit (FP32: the oracle on the
+    rounded bed, the state formed in FP32), and the clock starts at 0."""
+    sc = _amr_reservoir()
+    ps = "f32" if prec == gf.GF_FP32 else "f64"
+    ctx = gf.Context([sc], precision=prec, max_patches=512)
+    ctx.set_time(0, 123.0, 0.5)
+    print(f"set_initial, {ps}, 3 passes", flush=True)
+    st = ctx.set_initial(0, max_passes=3)
+    o = orc.Oracle(sc)
+    if prec == gf.GF_FP32:
+        o.set_bathy_f32(True)
+    init_oracle(o, sc, ps)
+    for _ in range(3):
+        f = o.tag()
+        if not f.any():
+            break
+        o.regrid(f)
+        init_oracle(o, sc, ps)
+    assert np.array_equal(ctx.leaves(0), o.leaves())
+    assert len(set(o.leaves()[:, 1])) >= 3
+    assert np.array_equal(st, o.state())
+    t, dt, steps, rej = ctx.time(0)
+    assert (t, dt, steps, rej) == (0.0, 0.0, 0, 0)
+    # zero passes: the recipe on the mesh as it is
+    ctx2 = gf.Context([sc], precision=prec, max_patches=512)
+    ctx2.set_leaves(0, o.leaves())
+    assert np.array_equal(ctx2.set_initial(0, max_passes=0), st)
+
+
+def test_set_initial_rejects_bad_arguments():
+    sc = _amr_reservoir()
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=512)
+    L = gf.load()
+    assert L.gf_set_initial(ctx._p, 0, gf.GF_IC_FN(0), None, 0) == gf.GF_E_INVALID
+    assert L.gf_set_initial(ctx._p, 3, gf.GF_IC_FN(lambda *a: None), None, 0) == gf.GF_E_INVALID
+    with pytest.raises(gf.GFError):
+        ctx.set_initial_fn(0, lambda *a: None, max_passes=-1)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_step_stats_report_courant_number_and_time(orc, plain):
+    """cfl_max of a call is the largest Courant number of its accepted
+    steps, the oracle's own figure bit for bit (FP64); seconds is the wall
+    time of the call."""
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=2, radius=300.0)
+    o = orc.Oracle(sc)
+    init_oracle(o, sc)
+    ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64)
+    ctx.set_state(0, o.state())
+    nu = o.advance(12)
+    t0 = time.perf_counter()
+    st = ctx.step(12, plain=plain)
+    wall = time.perf_counter() - t0
+    print(f"cfl_max {st.cfl_max!r} (oracle {float(nu.max())!r}), {st.seconds * 1e3:.2f} ms", flush=True)
+    assert st.steps == 12
+    assert st.cfl_max == float(nu.max())
+    assert 0.0 < st.seconds <= wall
+    assert np.array_equal(ctx.state(0)[:, :3], o.state()[:, :3])
+
+
+def test_tag_modes():
+    """GF_TAG_PLAIN is the criteria tagger; GF_TAG_LEARNED gives the network's
+    flags (the same as gf_net_predict) and needs parameters first."""
+    sc = _amr_reservoir()
+    ctx = gf.Context([sc], precision=gf.GF_FP32, max_patches=512)
+    ctx.set_initial(0, max_passes=2)
+    with pytest.raises(gf.GFError) as e:
+        ctx.tag(gf.GF_TAG_LEARNED)
+    assert e.value.code == gf.GF_E_STATE
+    with pytest.raises(gf.GFError):
+        ctx.tag(7)
+    ctx.net_set_params(inputs.cnn_init_params(4))
+    assert np.array_equal(ctx.tag(gf.GF_TAG_LEARNED), ctx.net_predict())
+    plain = ctx.tag(gf.GF_TAG_PLAIN)
+    assert np.array_equal(plain, ctx.tag())
+
+
+def test_train_step_on_device_batch_equals_host_batch():
+    """gf_net_train_step_dev on torch tensors (bfloat16 features, int8
+    labels) against gf_net_train_step on the same batch from host arrays:
+    the same parameters after each step and the same loss, bit for bit.  A
+    label outside 0..2 in the device batch weighs 0, the same as leaving the
+    sample out."""
+    import torch
+    rng = np.random.default_rng(8)
+    n = 48
+    X = (rng.standard_normal((n, 24, 24, 4)) * np.array([2.0, 0.5, 0.5, 1.0])).astype(np.float32)
+    y = rng.integers(0, 3, n).astype(np.int8)
+    cw = np.array([1.0, 0.5, 2.0])
+    params = inputs.cnn_init_params(5)
+    sc = inputs.reservoir_fractal(level=2, m=16, L=2000.0, seed=2, radius=300.0)
+    a = gf.Context([sc], precision=gf.GF_FP32, max_patches=64)
+    b = gf.Context([sc], precision=gf.GF_FP32, max_patches=64)
+    a.net_set_params(params)
+    b.net_set_params(params)
+    xt = torch.from_numpy(X.reshape(n, -1)).to("cuda").to(torch.bfloat16).view(torch.int16).contiguous()
+    # the host path rounds the same FP32 values to bfloat16 in the kernel
+    Xh = X.astype(np.float64)
+    yt = torch.from_numpy(y.copy()).to("cuda")
+    for it in range(3):
+        la = a.net_train_step(Xh, y, cw, lr=1e-3)
+        lb = b.net_train_step_dev(xt, yt, cw, lr=1e-3)
+        print(f"step {it}: loss host {la!r}, device {lb!r}", flush=True)
+        assert la == lb
+        assert np.array_equal(a.net_params(), b.net_params())
+    # an invalid label: the same as training without that sample
+    keep = np.ones(n, bool)
+    keep[[3, 17]] = False
+    y2 = y.copy()
+    y2[[3, 17]] = 5
+    la = a.net_train_step(Xh[keep], y[keep], cw, lr=1e-3)
+    lb = b.net_train_step_dev(xt, torch.from_numpy(y2).to("cuda"), cw, lr=1e-3)
+    assert la == lb
+    assert np.array_equal(a.net_params(), b.net_params())
+    with pytest.raises(ValueError):
+        b.net_train_step_dev(xt[:, :100], yt, cw, lr=1e-3)
