@@ -251,6 +251,20 @@ int gf_regrid(gf_ctx *ctx, const int8_t *flags_in, int64_t *n_leaves);
  * net volume that entered through non-wall physical boundaries. */
 int gf_mass(gf_ctx *ctx, int32_t scen, double *mass, double *clamp_volume, double *boundary_volume);
 
+/* The same mass budget for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): it
+ * calls no hipMalloc, hipFree or other allocating routine.  The per-patch
+ * partial volumes and the three results go to a static device array of
+ * 65536 + 64 doubles (512.5 KiB), one per GPU, held until the process ends;
+ * the sums are formed on the device in the same order and with the same
+ * operations as gf_mass, so the results equal gf_mass's bit for bit.  Every
+ * call on one GPU uses that GPU's array: calls that overlap on one GPU (other
+ * threads, other streams) race and must be serialised by the caller.
+ * Errors: GF_E_INVALID (more than 65536 patches over all scenarios of the
+ * context, bad scenario), GF_E_STATE (the mesh changed and no entry point has
+ * rebuilt its tables since: gf_step, gf_tag or gf_mass do), GF_E_HIP. */
+int gf_mass_static(gf_ctx *ctx, int32_t scen, double *mass, double *clamp_volume, double *boundary_volume);
+
 /* Clock of a scenario. */
 int gf_time(gf_ctx *ctx, int32_t scen, double *t, double *dt_next, int64_t *steps, int64_t *rejected);
 int gf_set_time(gf_ctx *ctx, int32_t scen, double t, double dt_next);

@@ -62,7 +62,7 @@ NET_FEATURES = 2304
 
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_initial", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain", "gf_step_lts",
-           "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_time", "gf_set_time", "gf_set_step_threads",
+           "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_mass_static", "gf_time", "gf_set_time", "gf_set_step_threads",
            "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
            "gf_net_forward", "gf_net_train_step", "gf_net_train_step_dev", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
 
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
     L.gf_set_initial.argtypes = [vp, i32, GF_IC_FN, vp, i32]
     L.gf_regrid.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(i64)]
     L.gf_mass.argtypes = [vp, i32, dp, dp, dp]
+    L.gf_mass_static.argtypes = [vp, i32, dp, dp, dp]
     L.gf_time.argtypes = [vp, i32, dp, dp, C.POINTER(i64), C.POINTER(i64)]
     L.gf_set_time.argtypes = [vp, i32, C.c_double, C.c_double]
     L.gf_set_step_threads.argtypes = [vp, i32]
@@ -316,6 +317,12 @@ class Context:
     def mass(self, scen: int = 0):
         m, c, b = C.c_double(), C.c_double(), C.c_double()
         self._chk(self.L.gf_mass(self._p, scen, C.byref(m), C.byref(c), C.byref(b)))
+        return np.array([m.value, c.value, b.value])
+
+    def mass_static(self, scen: int = 0):
+        """gf_mass_static: the mass budget without any allocation (static device scratch)."""
+        m, c, b = C.c_double(), C.c_double(), C.c_double()
+        self._chk(self.L.gf_mass_static(self._p, scen, C.byref(m), C.byref(c), C.byref(b)))
         return np.array([m.value, c.value, b.value])
 
     def time(self, scen: int = 0):

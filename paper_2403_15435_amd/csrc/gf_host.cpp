@@ -203,6 +203,9 @@ struct gf_ctx {
     struct GaugePoint { int32_t scen; double x, y; };
     std::vector<GaugePoint> gauges;
     std::string tune_cache;          // gf_config.autotune_cache, copied
+    // this device's copy of the static scratch (gf_mass_static), taken at creation
+    double *static_scratch = nullptr;
+    hipError_t static_err = hipSuccess;
     GaugeDev *d_gauges = nullptr;
     double *d_grec = nullptr;
     int64_t *d_gcount = nullptr;
@@ -1255,6 +1258,8 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
         gf_destroy(c);
         return GF_E_NOMEM;
     }
+    // the static scratch's address on this device, once, with the device current
+    c->static_err = gf_static_scratch(&c->static_scratch);
     std::vector<TagRules> rules;
     for (auto &s : c->sc) rules.push_back(s.rules);
     if (hipMemcpyAsync(c->d_rules, rules.data(), sizeof(TagRules) * rules.size(), hipMemcpyHostToDevice, c->stream) !=
@@ -2447,6 +2452,42 @@ int gf_set_initial(gf_ctx *c, int32_t scen, gf_ic_fn ic, void *user, int32_t max
     ScenDev &h = c->hs[(size_t)scen];
     h.t = 0.0; h.dt = 0.0; h.steps = 0; h.rejected = 0; h.status = 0; h.nu_max = 0.0;
     return push_scen(c);
+}
+
+int gf_mass_static(gf_ctx *c, int32_t scen, double *mass, double *clamp_volume, double *boundary_volume)
+{
+    int rc = check_scen(c, scen);
+    if (rc) return rc;
+    if (c->static_err != hipSuccess || !c->static_scratch)
+        return fail(c, GF_E_HIP, "static scratch unavailable: %s", hipGetErrorString(c->static_err));
+    // the tables must be current: rebuilding them may allocate
+    if (c->topo_dirty) return fail(c, GF_E_STATE, "mesh tables out of date (call gf_mass or gf_step once first)");
+    const int nw = (int)c->desc.size();
+    if (nw > gf::kStaticMassPatches)
+        return fail(c, GF_E_INVALID, "%d patches exceed the static scratch of %d patches", nw, gf::kStaticMassPatches);
+    double *part = c->static_scratch, *res = c->static_scratch + gf::kStaticMassPatches;
+    hipError_t e = hipSuccess;
+    if (nw > 0) {
+        if (c->prec == GF_FP32)
+            e = gf_launch_mass_f32(c->d_desc, nw, c->d_scen, (const float *)c->q[0], (const float *)c->q[1], c->cap, part,
+                                   c->m, c->stream);
+        else
+            e = gf_launch_mass_f64(c->d_desc, nw, c->d_scen, (const double *)c->q[0], (const double *)c->q[1], c->cap,
+                                   part, c->m, c->stream);
+    }
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "mass launch: %s", hipGetErrorString(e));
+    const int cur = c->hs[(size_t)scen].cur;
+    const Scen &S = c->sc[(size_t)scen];
+    e = gf_launch_mass_ordered(part, c->d_desc, nw, scen, c->cacc[cur], c->bacc[cur], S.clamp_base, S.bnd_base, res,
+                               c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "mass sum launch: %s", hipGetErrorString(e));
+    double out[3];
+    HIPCHK(c, hipMemcpyAsync(out, res, sizeof out, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (mass) *mass = out[0];
+    if (clamp_volume) *clamp_volume = out[1];
+    if (boundary_volume) *boundary_volume = out[2];
+    return GF_OK;
 }
 
 int gf_time(gf_ctx *c, int32_t scen, double *t, double *dt_next, int64_t *steps, int64_t *rejected)

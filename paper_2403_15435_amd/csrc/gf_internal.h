@@ -184,3 +184,14 @@ struct XferTaskH {
 
 GF_DECL_LAUNCHERS(f32, float)
 GF_DECL_LAUNCHERS(f64, double)
+
+// The entry point that allocates nothing (gf_mass_static, gf_static.hip):
+// device scratch for the per-patch partials of this many patches at most.
+namespace gf {
+constexpr int kStaticMassPatches = 1 << 16;
+}
+// address of this device's copy of the scratch array (call with the device current)
+hipError_t gf_static_scratch(double **ptr);
+// res[0..2] = volume, clamp volume, boundary volume of scenario `scen`
+hipError_t gf_launch_mass_ordered(const double *part, const gf::PatchDesc *d, int nw, int scen, const double *ca,
+                                  const double *ba, double clamp_base, double bnd_base, double *res, hipStream_t s);
