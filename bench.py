@@ -1,16 +1,21 @@
-"""Benchmark: cell updates per second of the FP32 patch update on one MI355X.
+"""Benchmark: cell updates per second of the FP32 batched adaptive patch
+update on one MI355X, against the plain FP64 path on the same inputs.
 
-Workload (one step = one full pass of ghost fill + wave-propagation update +
-friction + positivity + step control over every patch): uniform 2048 x 2048
-cells as 64 x 64 patches of 32 x 32 on a 10 km square of seeded fractal
-terrain (100 +/- 50 m), circular reservoir of depth 20 m and radius 400 m,
-Manning n = 0.033, walls.  A step is two kernels: the classification and
-update of dry patches, then the full update of the others.  Reported beside
-it: the same run on the plain FP64 path (ghost fill into ghosted tiles in
-device memory, a step launch per level, the step length chosen on the host:
-the comparator of the speedup) and on the fused FP64 path, the step's HBM
-roofline fraction (algorithmic 28 B per FP32 cell update), the same grid fully
-wet, and the CPU oracle timed on a bounded sample of the same workload.
+Headline workload (configuration 3, the adaptive one the metric names): the
+AMR inflow valley, 20 km x 10 km, side slope 0.05 with 2 m rms fractal
+roughness, 16 x 8 trees, levels 0-6 of 32 x 32 patches (finest cells 0.61 m,
+about 25 000 leaves), inflow 5000 m^3/s over 200 m on the hydrograph's
+plateau, Manning n = 0.04, extrapolation outflow, walls; the mesh built from
+level 0 by plain-tagger passes over the initial flood.  One step = one pass
+of ghost fill + wave-propagation update + friction + positivity + step control
++ refluxing over every leaf; the job tags and regrids every 4 steps, inside
+the timed window.  Reported beside it: the fused FP64 and plain FP64 paths on
+the same mesh and state, the step kernel's roofline (its launches timed alone
+with HIP events in a repeat of the window, the patches it updated counted in
+another), the device's achievable HBM bandwidth (a triad probe), the CPU
+oracle on the same valley (all host threads and one), and further sections:
+the uniform 2048^2 reservoir, the same grid fully wet, the 256-scenario
+ensemble, the floodplain, local time stepping, the learned tagger.
 """
 import argparse
 import json
@@ -25,9 +30,21 @@ sys.path.insert(0, ROOT)
 import numpy as np
 
 METRIC = "cell-updates/s and % HBM roofline, FP32-batched AMR vs FP64 plain, 1 MI355X"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_fp32_reservoir2048_hbm_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+VALLEY_COUNTERS = os.path.join(PROFILES, "step_kernel_fp32_valley_counters.txt")
+VALLEY_STATS = os.path.join(PROFILES, "step_kernel_fp32_valley_kernel_stats.txt")
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"f32": 28.0, "f64": 56.0}
+# the method's arithmetic per cell update (two augmented Riemann solves, three
+# limited waves and the transverse splits per edge direction, update and
+# friction), counted as VALU lane operations with sqrt and division as one
+ALGO_OPS_PER_UPDATE = 500.0
+# non-packed FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes per cycle x 2.4 GHz
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+VALLEY_DESC = ("AMR inflow valley (configuration 3): 20 km x 10 km V valley, side slope 0.05, 2 m rms fractal "
+               "roughness, 16x8 trees, levels 0-6 of 32x32 patches (finest cells 0.61 m), inflow 5000 m^3/s over "
+               "200 m (hydrograph plateau, from t = 4000 s), n = 0.04, extrapolation outflow, walls; mesh built "
+               "from level 0 by plain-tagger passes; tag and regrid every 4 steps inside the timed window")
 
 
 def workload():
@@ -40,131 +57,9 @@ def wet_workload():
     return inputs.wet_dambreak(level=6, m=32, L=10000.0, seed=2, radius=400.0, manning_n=0.033)
 
 
-def run_gpu(sc, precision, warmup, steps, step_threads=None, wet_fraction=False, plain=False):
-    import torch
-    import paper_2403_15435_amd as gf
-    ctx = gf.Context([sc], precision=precision, max_patches=4096)
-    ctx.set_initial(0)
-    ctx.step(warmup, plain=plain)
-    tuned = None
-    if plain:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.step(steps, plain=True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        out = {"wall": wall, "cell_updates": int(st.cell_updates), "steps": int(st.steps),
-               "rejected": int(st.rejected), "mass": ctx.mass(0).tolist()}
-        ctx.close()
-        return out
-    if step_threads:
-        ctx.set_step_threads(step_threads)
-    else:
-        # launch shape from the tuner (state restored after its trials)
-        tuned = ctx.autotune(steps=5)
-    torch.cuda.synchronize()
-    # the timed run: HIP events on the library's stream bracket its launches
-    # (nothing is queued between the kernels); a second run of the same window
-    # (state and clock restored) has the kernels count patches
-    state0 = ctx.state(0)[:, :3]
-    t_0, dt_0 = ctx.time(0)[:2]
-    ctx.profile_enable(True)
-    t0 = time.perf_counter()
-    st = ctx.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launches, ms = ctx.profile_read()
-    ctx.profile_enable(False)
-    cells = int(st.cell_updates)
-    ctx.set_state(0, state0)
-    ctx.set_time(0, t_0, dt_0)
-    ctx.profile_enable(False, patches=True)
-    st2 = ctx.step(steps)
-    torch.cuda.synchronize()
-    full, stable = ctx.profile_patches()
-    ctx.profile_enable(False)
-    assert int(st2.cell_updates) == cells
-    mass = ctx.mass(0)
-    out = {"wall": wall, "cell_updates": cells, "steps": int(st.steps), "launches": launches, "kernel_ms": ms,
-           "rejected": int(st.rejected), "mass": mass.tolist(), "step_threads": ctx.step_threads(), "tuned": tuned,
-           "full_patch_updates": full, "stable_dry_patches": stable}
-    if wet_fraction:
-        h = ctx.state(0)[:, 0]
-        out["wet_cell_fraction"] = float(np.count_nonzero(h > 1e-4)) / h.size
-    ctx.close()
-    return out
-
-
 def _sync():
     import torch
     torch.cuda.synchronize()
-
-
-def valley_amr(steps, warmup, regrid_every=4, t0=4000.0):
-    """The AMR workload: the inflow valley (20 km x 10 km, 16 x 8 trees, levels
-    0-6 of 32 x 32 patches, finest cells 0.61 m), refined from level 0 around
-    its normal-depth flood by the plain tagger, started on the hydrograph's
-    plateau (5000 m^3/s); tag and regrid every `regrid_every` steps.  Run on
-    the fused FP32 path, the fused FP64 path and the plain FP64 path from the
-    same mesh and state (the FP32 one, widened)."""
-    import paper_2403_15435_amd as gf
-    from paper_2403_15435_amd import inputs
-    sc = inputs.v_valley()
-    cap = 48000
-    base = gf.Context([sc], precision=gf.GF_FP32, max_patches=cap)
-    base.set_initial(0)
-    for _ in range(sc.max_level - sc.min_level):
-        base.tag()
-        base.regrid(None)
-        base.set_initial(0)
-    leaves0, state0 = base.leaves(0), base.state(0)
-    base.close()
-    print(f"[bench] valley mesh: {leaves0.shape[0]} leaves, levels {sorted(set(leaves0[:, 1].tolist()))}",
-          file=sys.stderr, flush=True)
-    out = {"workload": "AMR inflow valley: 20 km x 10 km V valley (side slope 0.05, 2 m rms fractal roughness), "
-                       "16x8 trees, levels 0-6 of 32x32 patches (finest 0.61 m), inflow 5000 m^3/s over 200 m, "
-                       "n = 0.04, extrapolation outflow, walls; plain tagger and regrid every 4 steps",
-           "leaves_start": int(leaves0.shape[0]), "steps": steps, "regrid_every": regrid_every}
-    for name, prec, plain in (("fp32_fused", gf.GF_FP32, False), ("fp64_fused", gf.GF_FP64, False),
-                              ("fp64_plain", gf.GF_FP64, True)):
-        ctx = gf.Context([sc], precision=prec, max_patches=cap)
-        ctx.set_leaves(0, leaves0)
-        ctx.set_state(0, state0[:, :3])
-        ctx.set_time(0, t0)
-        if not plain:
-            ctx.autotune(steps=3)
-
-        def cycle():
-            _sync()
-            a = time.perf_counter()
-            st = ctx.step(regrid_every, plain=plain)
-            _sync()
-            b = time.perf_counter()
-            ctx.tag()
-            ctx.regrid(None)
-            return st, b - a, time.perf_counter() - b
-        for _ in range(max(warmup // regrid_every, 1)):
-            cycle()
-        m0 = ctx.mass(0)
-        t_step = t_regrid = 0.0
-        cells = 0
-        for _ in range(steps // regrid_every):
-            st, ts, tr = cycle()
-            t_step += ts
-            t_regrid += tr
-            cells += int(st.cell_updates)
-        M = ctx.mass(0)
-        cups = cells / t_step
-        out[name] = {"step_cell_updates_per_s": cups, "end_to_end_cell_updates_per_s": cells / (t_step + t_regrid),
-                     "step_s": t_step, "tag_regrid_s": t_regrid, "leaves_end": int(ctx.leaves(0).shape[0]),
-                     "budget_residual_rel": float(((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) / M[0])}
-        if prec == gf.GF_FP32:
-            out[name]["hbm_frac_algorithmic"] = cups * BYTES_PER_UPDATE["f32"] / (HBM_PEAK_GBS * 1e9)
-        print(f"[bench] valley {name}: {out[name]}", file=sys.stderr, flush=True)
-        ctx.close()
-    out["speedup_fp32_fused_over_fp64_plain"] = (out["fp32_fused"]["step_cell_updates_per_s"]
-                                                 / out["fp64_plain"]["step_cell_updates_per_s"])
-    return out
 
 
 def flood_speed_amr(steps, warmup, regrid_every=4, t_spin=1800.0):
@@ -441,79 +336,308 @@ def learned_tagger(n_train=50, n_eval=10, steps=2000, window=16, check=4, iters=
             "modes": acc}
 
 
-def guarded(fn, *a):
+def guarded(fn, *a, **kw):
     """An extra workload's section, or the error that stopped it."""
     try:
-        return fn(*a)
+        return fn(*a, **kw)
     except Exception as e:  # reported in the JSON line, which still prints
         print(f"[bench] {fn.__name__} failed: {e!r}", file=sys.stderr, flush=True)
         return {"error": repr(e)}
 
 
-def cpu_baseline(sc, steps=48):
+
+def valley_mesh():
+    """The valley, its mesh built from level 0 by gf_set_initial's plain-tagger
+    passes (FP32 state)."""
+    import paper_2403_15435_amd as gf
+    from paper_2403_15435_amd import inputs
+    sc = inputs.v_valley()
+    base = gf.Context([sc], precision=gf.GF_FP32, max_patches=48000)
+    base.set_initial(0, max_passes=sc.max_level - sc.min_level)
+    leaves, state = base.leaves(0), base.state(0)
+    base.close()
+    print(f"[bench] valley mesh: {leaves.shape[0]} leaves, levels {np.bincount(leaves[:, 1]).tolist()}",
+          file=sys.stderr, flush=True)
+    return sc, leaves, state
+
+
+def amr_window(ctx, steps, regrid_every=4, plain=False):
+    """`steps` steps with a plain tag and regrid after every `regrid_every`
+    (the adaptive job).  Returns (cell updates, wall time of the whole window,
+    time inside the step calls, accepted steps, rejected attempts); each call
+    returns synchronised."""
+    cells, t_step, done, acc, rej = 0, 0.0, 0, 0, 0
+    _sync()
+    t0 = time.perf_counter()
+    while done < steps:
+        n = min(regrid_every, steps - done)
+        a = time.perf_counter()
+        st = ctx.step(n, plain=plain)
+        t_step += time.perf_counter() - a
+        cells += int(st.cell_updates)
+        acc += int(st.steps)
+        rej += int(st.rejected)
+        done += n
+        ctx.tag()
+        ctx.regrid(None)
+    _sync()
+    return cells, time.perf_counter() - t0, t_step, acc, rej
+
+
+def _restore(ctx, snap):
+    leaves, state, t, dt = snap
+    ctx.set_leaves(0, leaves)
+    ctx.set_state(0, state[:, :3])
+    ctx.set_time(0, t, dt)
+
+
+def valley_headline(steps, warmup, regrid_every=4, t0=4000.0, paths=("fp32_fused", "fp64_fused", "fp64_plain")):
+    """The headline: the valley on the fused FP32 path (the timed window),
+    then the same window again with the step kernel's launches timed alone,
+    and once more with the kernels counting the patches they update; the
+    fused FP64 and plain FP64 paths from the same mesh and state."""
+    import paper_2403_15435_amd as gf
+    sc, leaves0, state0 = valley_mesh()
+    cap = 48000
+    out = {"workload": VALLEY_DESC, "leaves_start": int(leaves0.shape[0]),
+           "levels_start": np.bincount(leaves0[:, 1]).tolist(), "steps": steps, "regrid_every": regrid_every}
+    snap = None
+    for name in paths:
+        prec = gf.GF_FP32 if name == "fp32_fused" else gf.GF_FP64
+        plain = name == "fp64_plain"
+        ctx = gf.Context([sc], precision=prec, max_patches=cap)
+        if snap is None:
+            _restore(ctx, (leaves0, state0, t0, 0.0))
+        else:
+            _restore(ctx, snap)
+        res = {}
+        if not plain:
+            res["tuned"] = list(ctx.autotune(steps=3))
+        if snap is None:
+            # the warm-up, then the window every path starts from
+            amr_window(ctx, warmup, regrid_every)
+            snap = (ctx.leaves(0), ctx.state(0), *ctx.time(0)[:2])
+            _restore(ctx, snap)
+        else:
+            amr_window(ctx, min(warmup, 8), regrid_every, plain)
+            _restore(ctx, snap)
+        m0 = ctx.mass(0)
+        cells, wall, t_step, acc, rej = amr_window(ctx, steps, regrid_every, plain)
+        M = ctx.mass(0)
+        res.update({"cell_updates_per_s": cells / wall, "step_cell_updates_per_s": cells / t_step,
+                    "wall_s": wall, "step_s": t_step, "tag_regrid_s": wall - t_step, "cell_updates": cells,
+                    "accepted_steps": acc, "rejected": rej, "leaves_end": int(ctx.leaves(0).shape[0]),
+                    "budget_residual_rel": float(((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) / M[0])})
+        if name == "fp32_fused":
+            res["step_threads"] = ctx.step_threads()
+            # repeat 1: the step kernel's launches timed alone (event pairs)
+            _restore(ctx, snap)
+            ctx.profile_enable(False, kernel=True)
+            c2 = amr_window(ctx, steps, regrid_every)[0]
+            n_launch, ms = ctx.profile_kernel()
+            ctx.profile_enable(False)
+            # repeat 2: the patches the step kernel updated
+            _restore(ctx, snap)
+            ctx.profile_enable(False, patches=True)
+            c3 = amr_window(ctx, steps, regrid_every)[0]
+            full, stable = ctx.profile_patches()
+            ctx.profile_enable(False)
+            res.update({"repeat_cell_updates_equal": bool(c2 == cells and c3 == cells),
+                        "step_kernel_launches": n_launch, "step_kernel_avg_us": 1e3 * ms / max(n_launch, 1),
+                        "patches_full_update": full, "patches_stable_dry": stable})
+        print(f"[bench] valley {name}: {res}", file=sys.stderr, flush=True)
+        out[name] = res
+        ctx.close()
+    if "fp64_plain" in out and "fp32_fused" in out:
+        out["speedup_fp32_fused_over_fp64_plain"] = (out["fp32_fused"]["cell_updates_per_s"]
+                                                     / out["fp64_plain"]["cell_updates_per_s"])
+        out["speedup_step_fp32_fused_over_fp64_plain"] = (out["fp32_fused"]["step_cell_updates_per_s"]
+                                                          / out["fp64_plain"]["step_cell_updates_per_s"])
+    if "fp64_fused" in out and "fp32_fused" in out:
+        out["speedup_fp32_over_fp64_fused"] = (out["fp32_fused"]["cell_updates_per_s"]
+                                               / out["fp64_fused"]["cell_updates_per_s"])
+    return out
+
+
+def run_reservoir(sc, precision, warmup, steps, plain=False):
+    """The uniform 2048^2 reservoir (a further section): `steps` steps timed on
+    the host clock; the fused path's step kernel timed alone in a repeat of
+    the window, and the patches it updated counted in another."""
+    import paper_2403_15435_amd as gf
+    ctx = gf.Context([sc], precision=precision, max_patches=4096)
+    ctx.set_initial(0)
+    if not plain:
+        ctx.autotune(steps=5)
+    ctx.step(warmup, plain=plain)
+    state0 = ctx.state(0)[:, :3]
+    t_0, dt_0 = ctx.time(0)[:2]
+    _sync()
+    t0 = time.perf_counter()
+    st = ctx.step(steps, plain=plain)
+    _sync()
+    wall = time.perf_counter() - t0
+    out = {"wall": wall, "cell_updates": int(st.cell_updates), "steps": int(st.steps), "rejected": int(st.rejected)}
+    if not plain:
+        for kw in ({"kernel": True}, {"patches": True}):
+            ctx.set_state(0, state0)
+            ctx.set_time(0, t_0, dt_0)
+            ctx.profile_enable(False, **kw)
+            ctx.step(steps)
+            if "kernel" in kw:
+                n, ms = ctx.profile_kernel()
+                out["step_kernel_launches"], out["step_kernel_avg_us"] = n, 1e3 * ms / max(n, 1)
+            else:
+                out["patches_full_update"], out["patches_stable_dry"] = ctx.profile_patches()
+            ctx.profile_enable(False)
+        out["step_threads"] = ctx.step_threads()
+        h = ctx.state(0)[:, 0]
+        out["wet_cell_fraction_end"] = float(np.count_nonzero(h > 1e-4)) / h.size
+    ctx.close()
+    return out
+
+
+def reservoir_section(steps, warmup, wet_steps):
+    """The uniform reservoir (most patches dry or stable, a few hundred
+    updated per step) and the same grid fully wet, FP32 fused, FP64 fused and
+    FP64 plain."""
+    import paper_2403_15435_amd as gf
+    sc = workload()
+    out = {"workload": "uniform 2048x2048 cells (64x64 patches of 32x32), 10 km fractal terrain 100+/-50 m, "
+                       "reservoir h=20 m r=400 m, n=0.033, walls, adaptive CFL 0.9", "steps": steps}
+    r32 = run_reservoir(sc, gf.GF_FP32, warmup, steps)
+    r64 = run_reservoir(sc, gf.GF_FP64, warmup, steps)
+    rp = run_reservoir(sc, gf.GF_FP64, warmup, steps, plain=True)
+    cups = {k: v["cell_updates"] / v["wall"] for k, v in (("fp32_fused", r32), ("fp64_fused", r64), ("fp64_plain", rp))}
+    upd = r32["patches_full_update"] * 1024 / max(r32["step_kernel_launches"], 1)
+    t = r32["step_kernel_avg_us"] * 1e-6
+    out.update({"cell_updates_per_s": cups, "fp32_fused": r32,
+                "speedup_fp32_fused_over_fp64_plain": cups["fp32_fused"] / cups["fp64_plain"],
+                "step_kernel_cells_updated_per_launch": upd,
+                "step_kernel_hbm_frac": BYTES_PER_UPDATE["f32"] * upd / t / 1e9 / HBM_PEAK_GBS,
+                "dense_equivalent_hbm_frac": BYTES_PER_UPDATE["f32"] * 4096 * 1024 / t / 1e9 / HBM_PEAK_GBS})
+    if wet_steps > 0:
+        w32 = run_reservoir(wet_workload(), gf.GF_FP32, 10, wet_steps)
+        tw = w32["step_kernel_avg_us"] * 1e-6
+        out["all_wet"] = {"workload": "same grid and terrain under a lake at 155 m (every cell wet), column at 165 m",
+                          "fp32_cell_updates_per_s": w32["cell_updates"] / w32["wall"],
+                          "step_kernel_avg_us": w32["step_kernel_avg_us"],
+                          "step_kernel_hbm_frac": BYTES_PER_UPDATE["f32"] * 4096 * 1024 / tw / 1e9 / HBM_PEAK_GBS}
+    print(f"[bench] reservoir: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+# the learned-tagger section: bounded by default (a few seeds and a shorter
+# run), the full configuration (50 training and 10 evaluation seeds) on request
+LEARNED = {"small": dict(n_train=4, n_eval=2, steps=400, iters=200),
+           "full": dict(n_train=50, n_eval=10, steps=2000, iters=400)}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(t0=4000.0, steps_all=4, steps_one=2):
+    """The oracle on the same valley (its own mesh from the same refinement
+    passes; it takes nothing from the GPU path): `steps_all` adaptive steps on
+    every host thread OpenMP offers (OMP_NUM_THREADS, or every core), then
+    `steps_one` on one thread."""
     import oracle
+    from paper_2403_15435_amd import inputs
     from paper_2403_15435_amd.inputs import initial_state
     oracle.build(force=False)
+    sc = inputs.v_valley()
     o = oracle.Oracle(sc)
-    lv = o.leaves()
-    for k in range(lv.shape[0]):
-        h, hu, hv = initial_state(sc, lv[k], o.get_field(k, 3), "f64")
-        o.set_field(k, 0, np.asarray(h, np.float64))
-        o.set_field(k, 1, np.asarray(hu, np.float64))
-        o.set_field(k, 2, np.asarray(hv, np.float64))
-    t0 = time.perf_counter()
-    o.advance(steps)
-    dt = time.perf_counter() - t0
-    cells = o.steps * lv.shape[0] * sc.m * sc.m
-    return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{o.steps} adaptive steps of the full 2048^2 workload (FP64, one thread), {dt:.1f} s"}
+
+    def recipe():
+        lv = o.leaves()
+        for k in range(lv.shape[0]):
+            h, hu, hv = initial_state(sc, lv[k], o.get_field(k, 3), "f64")
+            o.set_field(k, 0, np.asarray(h, np.float64))
+            o.set_field(k, 1, np.asarray(hu, np.float64))
+            o.set_field(k, 2, np.asarray(hv, np.float64))
+    recipe()
+    for _ in range(sc.max_level - sc.min_level):
+        f = o.tag()
+        if not f.any():
+            break
+        o.regrid(f)
+        recipe()
+    o.set_time(t0, 0.0)
+    n_leaves = o.n_leaves
+    res = {}
+    for label, nt, steps in (("all", 0, steps_all), ("one", 1, steps_one)):
+        used = oracle.set_threads(nt)
+        s0 = o.steps
+        a = time.perf_counter()
+        o.advance(steps)
+        dt = time.perf_counter() - a
+        res[label] = {"threads": used, "steps": o.steps - s0, "s": dt,
+                      "cell_updates_per_s": (o.steps - s0) * n_leaves * sc.m * sc.m / dt}
+    oracle.set_threads(0)
+    return {"value": res["all"]["cell_updates_per_s"], "unit": "cell-updates/s", "cores": res["all"]["threads"],
+            "kind": "oracle",
+            "sample": (f"{res['all']['steps']} adaptive steps of the valley ({n_leaves} leaves, levels 0-6, its own "
+                       f"mesh from the same refinement passes; FP64) on {res['all']['threads']} threads "
+                       f"({res['all']['s']:.1f} s), then {res['one']['steps']} on one thread ({res['one']['s']:.1f} s)"),
+            "one_thread_cell_updates_per_s": res["one"]["cell_updates_per_s"],
+            "host": {"cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+                     "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}}
 
 
-def measured_traffic():
-    """HBM bytes per step (both kernels) from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, scaled by the copy-kernel calibration; None
-    when the summary was taken on different kernel sources."""
+def read_summary(path):
+    """Key: value lines of a committed profile summary, or None when it is
+    missing or was taken on other kernel sources."""
     from paper_2403_15435_amd.build import source_digest
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and not line.startswith("#"):
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", " ")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("source_digest") != source_digest():
         return None
+    return kv
+
+
+def _num(kv, key):
     try:
-        fetch = float(kv["fetch_kib_per_step"]) * float(kv["fetch_scale"])
-        write = float(kv["write_kib_per_step"]) * float(kv["write_scale"])
-    except (KeyError, ValueError):
+        return float(kv[key]) if kv and key in kv else None
+    except ValueError:
         return None
-    return (fetch + write) * 1024.0
 
 
-def profiled_kernel_us():
-    """Average durations (us) of the reservoir FP32 dry and step kernels in
-    the committed rocprofv3 kernel-trace summary; None when it was taken on
-    other kernel sources."""
-    from paper_2403_15435_amd.build import source_digest
-    path = os.path.join(ROOT, "profiles", "step_reservoir2048_kernel_stats.txt")
-    if not os.path.exists(path):
-        return None
-    text = open(path).read()
-    if source_digest() not in text or "Reservoir, FP32:" not in text:
-        return None
-    block = text.split("Reservoir, FP32:")[1].split("\n\n")[0]
-    out = {}
-    for line in block.splitlines():
-        f = line.split()
-        if "avg_ns" not in f:
-            continue
-        avg = float(f[f.index("avg_ns") + 1]) * 1e-3
-        if "dry_kernel<32>" in line:
-            out["dry_kernel_us"] = avg
-        elif "step_kernel<32," in line and "512>" in line:
-            out["step_kernel_us"] = avg
-    return out or None
+def triad_probe(n=1 << 28, reps=10):
+    """Achievable HBM bandwidth: the library's triad kernel c = a + s b on
+    three arrays of n floats (3 GiB), `reps` launches each timed with a HIP
+    event pair on the stream it runs on; 12 n bytes per launch."""
+    import torch
+    import paper_2403_15435_amd as gf
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.full((n,), 2.0, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    gf.probe_triad(a, b, c)
+    torch.cuda.synchronize()
+    assert float(c[0]) == 7.0 and float(c[-1]) == 7.0
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gf.probe_triad(a, b, c)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    gbs = [12.0 * n / t / 1e9 for t in times]
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"kernel": "gf_probe_triad (c = a + s b, float4 grid-stride)", "bytes_per_launch": 12 * n,
+            "best_GBps": max(gbs), "median_GBps": float(np.median(gbs)), "launches": reps}
 
 
 def calibrate_copy(mib=512, reps=5):
@@ -530,27 +654,64 @@ def calibrate_copy(mib=512, reps=5):
     print(json.dumps({"copy_kib_read": mib * 1024, "copy_kib_written": mib * 1024, "reps": reps}))
 
 
+def roofline(v32, probe):
+    """The step kernel's roofline from the headline's repeats: cells it
+    updated per launch (patch counts), its average launch (event pairs); the
+    issued VALU operations and HBM bytes per launch from the committed counter
+    summary of this workload when it matches the kernel sources; the bound
+    from those counters."""
+    n = max(v32["step_kernel_launches"], 1)
+    t = v32["step_kernel_avg_us"] * 1e-6
+    cells = v32["patches_full_update"] * 1024.0 / n
+    dense = v32["cell_updates"] / max(v32["accepted_steps"] + v32["rejected"], 1)
+    alg_ops = ALGO_OPS_PER_UPDATE * cells
+    hbm_gbs = BYTES_PER_UPDATE["f32"] * cells / t / 1e9
+    kv = read_summary(VALLEY_COUNTERS)
+    stats = read_summary(VALLEY_STATS)
+    valu_per_launch = _num(kv, "valu_lane_ops_per_launch")
+    traffic = None
+    if kv and _num(kv, "fetch_kib_per_launch") is not None:
+        traffic = 1024.0 * (_num(kv, "fetch_kib_per_launch") * _num(kv, "fetch_scale")
+                            + _num(kv, "write_kib_per_launch") * _num(kv, "write_scale"))
+    issued_frac = valu_per_launch / t / 1e9 / VALU_PEAK_GOPS if valu_per_launch else None
+    traffic_frac = traffic / t / 1e9 / HBM_PEAK_GBS if traffic else None
+    if issued_frac is not None and traffic_frac is not None:
+        bound, source = ("alu", "counters") if issued_frac >= traffic_frac else ("hbm", "counters")
+    else:
+        bound, source = "alu", "no counters for these kernel sources: the method's arithmetic intensity"
+    achieved = alg_ops / t / 1e9
+    return {"bound": bound, "bound_from": source, "achieved": achieved, "peak": VALU_PEAK_GOPS,
+            "unit": "Gop/s (VALU lane operations, non-packed FP32)", "frac": achieved / VALU_PEAK_GOPS,
+            "traffic": traffic, "traffic_unit": "HBM bytes per launch (counters x copy calibration)",
+            "kernel": f"step_kernel<32,{v32.get('step_threads')}> fp32", "launches": n,
+            "avg_launch_us": t * 1e6, "rocprof_avg_launch_us": _num(stats, "step_kernel_avg_us"),
+            "cells_updated_per_launch": cells, "algorithmic_ops_per_cell": ALGO_OPS_PER_UPDATE,
+            "algorithmic_ops_per_launch": alg_ops,
+            "issued_valu_ops_per_cell": valu_per_launch / cells if valu_per_launch else None,
+            "issued_valu_frac": issued_frac,
+            "hbm": {"algorithmic_bytes_per_launch": BYTES_PER_UPDATE["f32"] * cells, "achieved": hbm_gbs,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS,
+                    "frac_of_achievable": hbm_gbs / probe["best_GBps"] if probe else None,
+                    "traffic_frac": traffic_frac,
+                    "dense_equivalent_frac": BYTES_PER_UPDATE["f32"] * dense / t / 1e9 / HBM_PEAK_GBS},
+            "hbm_achievable": probe}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--fp64-steps", type=int, default=0, help="steps of the FP64 run (0: the same as --steps)")
+    ap.add_argument("--steps", type=int, default=400, help="timed steps of the headline valley window")
+    ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--step-threads", type=int, default=0, help="step-kernel workgroup size (0: chosen by the tuner)")
-    ap.add_argument("--workload", choices=["reservoir", "wet"], default="reservoir",
-                    help="run only this grid (counter collection); the JSON line is for the reservoir")
-    ap.add_argument("--wet-steps", type=int, default=200, help="steps of the all-wet comparison run (0: skip)")
-    ap.add_argument("--precision", choices=["both", "f32", "f64", "plain"], default="both",
-                    help="run only one path (for counter collection; plain: the FP64 comparator); "
-                         "the JSON line needs all")
-    ap.add_argument("--plain-steps", type=int, default=0, help="steps of the plain FP64 run (0: the same as --steps)")
-    ap.add_argument("--amr-steps", type=int, default=400, help="steps of each AMR valley run (0: skip)")
+    ap.add_argument("--reservoir-steps", type=int, default=2000, help="steps of the uniform reservoir section (0: skip)")
+    ap.add_argument("--wet-steps", type=int, default=200, help="steps of the all-wet run (0: skip)")
     ap.add_argument("--ensemble-steps", type=int, default=200, help="steps of each ensemble run (0: skip)")
     ap.add_argument("--flood-steps", type=int, default=400, help="steps of each floodplain AMR run (0: skip)")
     ap.add_argument("--lts-steps", type=int, default=64, help="single-clock steps of the local-time-stepping window (0: skip)")
-    ap.add_argument("--only", choices=["valley", "ensemble", "learned", "flood", "lts"], default=None,
-                    help="run only this extra workload and print its section")
+    ap.add_argument("--learned", choices=["off", "small", "full"], default="small",
+                    help="learned-tagger section: small (a few seeds, bounded), full (50 + 10 seeds)")
+    ap.add_argument("--only", choices=["valley", "fp32", "reservoir", "ensemble", "learned", "flood", "lts", "triad"],
+                    default=None, help="run only this section and print it (fp32: the headline's FP32 path only)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -560,113 +721,54 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
-    if args.only == "valley":
-        print(json.dumps(valley_amr(args.amr_steps, 40)))
+    only = {"valley": lambda: valley_headline(args.steps, args.warmup),
+            "fp32": lambda: valley_headline(args.steps, args.warmup, paths=("fp32_fused",)),
+            "reservoir": lambda: reservoir_section(args.reservoir_steps, 50, args.wet_steps),
+            "ensemble": lambda: ensemble(args.ensemble_steps, 10),
+            "lts": lambda: lts_compare(args.lts_steps),
+            "flood": lambda: flood_speed_amr(args.flood_steps, 40),
+            "learned": lambda: learned_tagger(**LEARNED[args.learned if args.learned != "off" else "small"]),
+            "triad": triad_probe}
+    if args.only:
+        print(json.dumps(only[args.only]()))
         return
-    if args.only == "ensemble":
-        print(json.dumps(ensemble(args.ensemble_steps, 10)))
-        return
-    if args.only == "lts":
-        print(json.dumps(lts_compare(args.lts_steps)))
-        return
-    if args.only == "flood":
-        print(json.dumps(flood_speed_amr(args.flood_steps, 40)))
-        return
-    if args.only == "learned":
-        print(json.dumps(learned_tagger()))
-        return
-    import paper_2403_15435_amd as gf
-    sc = workload() if args.workload == "reservoir" else wet_workload()
-    print(f"[bench] workload ready: {sc.name}, {4096} patches", file=sys.stderr, flush=True)
-    nt = args.step_threads or None
-    if args.fp64_steps <= 0:
-        args.fp64_steps = args.steps
-    if args.plain_steps <= 0:
-        args.plain_steps = args.steps
-    if args.precision == "plain":
-        rp = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.plain_steps, plain=True)
-        print(f"[bench] plain fp64 done: {rp}", file=sys.stderr, flush=True)
-        return
-    if args.precision == "f64":
-        r64 = run_gpu(sc, gf.GF_FP64, min(args.warmup, 20), args.fp64_steps, nt)
-        print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
-        return
-    r32 = run_gpu(sc, gf.GF_FP32, args.warmup, args.steps, nt, wet_fraction=True)
-    print(f"[bench] fp32 done: {r32}", file=sys.stderr, flush=True)
-    if args.precision == "f32":
-        return
-    r64 = run_gpu(sc, gf.GF_FP64, args.warmup, args.fp64_steps, nt)
-    print(f"[bench] fp64 done: {r64}", file=sys.stderr, flush=True)
-    rp = run_gpu(sc, gf.GF_FP64, args.warmup, args.plain_steps, plain=True)
-    print(f"[bench] plain fp64 done: {rp}", file=sys.stderr, flush=True)
-    wet = None
-    if args.wet_steps > 0:
-        wsc = wet_workload()
-        w32 = run_gpu(wsc, gf.GF_FP32, 10, args.wet_steps, nt)
-        w64 = run_gpu(wsc, gf.GF_FP64, 10, max(args.wet_steps // 2, 1), nt)
-        print(f"[bench] all-wet fp32 {w32}\n[bench] all-wet fp64 {w64}", file=sys.stderr, flush=True)
-        wl = w32["kernel_ms"] / max(w32["launches"], 1) / 1e3
-        wet = {"workload": "same grid and terrain under a lake at 155 m (every cell wet), column at 165 m r=400 m",
-               "fp32_cell_updates_per_s": w32["cell_updates"] / w32["wall"],
-               "fp64_cell_updates_per_s": w64["cell_updates"] / w64["wall"],
-               "fp32_step_us": wl * 1e6,
-               "fp32_hbm_frac": BYTES_PER_UPDATE["f32"] * 4096 * 1024 / wl / 1e9 / HBM_PEAK_GBS,
-               "step_threads": w32["step_threads"]}
-    cups32 = r32["cell_updates"] / r32["wall"]
-    cups64 = r64["cell_updates"] / r64["wall"]
-    cupsp = rp["cell_updates"] / rp["wall"]
-    cells_per_launch = 4096 * 32 * 32
-    avg_launch_s = r32["kernel_ms"] / max(r32["launches"], 1) / 1e3
-    achieved = BYTES_PER_UPDATE["f32"] * cells_per_launch / avg_launch_s / 1e9
-    rp_us = profiled_kernel_us()
-    rp_step = rp_us["dry_kernel_us"] + rp_us["step_kernel_us"] if rp_us and len(rp_us) == 2 else None
-    amr = guarded(valley_amr, args.amr_steps, 40) if args.amr_steps > 0 else None
+    probe = triad_probe()
+    print(f"[bench] triad probe: {probe}", file=sys.stderr, flush=True)
+    v = valley_headline(args.steps, args.warmup)
+    v32 = v["fp32_fused"]
+    res = guarded(reservoir_section, args.reservoir_steps, 50, args.wet_steps) if args.reservoir_steps > 0 else None
     ens = guarded(ensemble, args.ensemble_steps, 10) if args.ensemble_steps > 0 else None
     flood = guarded(flood_speed_amr, args.flood_steps, 40) if args.flood_steps > 0 else None
     ltsc = guarded(lts_compare, args.lts_steps) if args.lts_steps > 0 else None
+    learned = guarded(learned_tagger, **LEARNED[args.learned]) if args.learned != "off" else None
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(sc)
+        cpu = guarded(cpu_baseline)
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
     line = {
-        "metric": METRIC, "value": cups32, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * r32["wall"] / max(r32["steps"], 1),
+        "metric": METRIC, "value": v32["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * v32["wall_s"] / max(args.steps, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "uniform 2048x2048 cells (64x64 patches of 32x32), 10 km fractal terrain 100+/-50 m, "
-                               "reservoir h=20 m r=400 m, n=0.033, walls, adaptive CFL 0.9",
-                   "patches": 4096, "cells": cells_per_launch},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "traffic_unit": "HBM bytes per launch (counters x copy calibration)",
-                     "algorithmic_bytes_per_launch": BYTES_PER_UPDATE["f32"] * cells_per_launch,
-                     "kernel": f"one step = dry_kernel<32> + step_kernel<32,{r32['step_threads']}> (fp32)",
-                     # event pair on the library's stream around the timed launches, per step
-                     "avg_launch_us": avg_launch_s * 1e6,
-                     # the same kernels as rocprofv3 times them (committed summary of this command)
-                     # and their sum, which the event figure above includes with the gaps between
-                     # launches
-                     "rocprof_kernel_us": rp_us,
-                     "rocprof_step_us": rp_step,
-                     "patches_full_update_per_step": r32["full_patch_updates"] / max(r32["launches"], 1),
-                     "patches_stable_dry_per_step": r32["stable_dry_patches"] / max(r32["launches"], 1),
-                     "step_kernel_hbm_frac": (BYTES_PER_UPDATE["f32"] * 1024 * r32["full_patch_updates"]
-                                              / max(r32["launches"], 1)
-                                              / (1e-6 * rp_us["step_kernel_us"]) / 1e9 / HBM_PEAK_GBS
-                                              if rp_us and "step_kernel_us" in rp_us else None)},
-        "fp64_plain": {"value": cupsp, "unit": "cell-updates/s", "steps": rp["steps"],
+        "config": {"workload": VALLEY_DESC, "leaves": v["leaves_start"], "levels": v["levels_start"],
+                   "cells_per_step": v["leaves_start"] * 1024, "regrid_every": 4},
+        "roofline": roofline(v32, probe),
+        "step_cell_updates_per_s": v32["step_cell_updates_per_s"],
+        "fp64_plain": {"value": v["fp64_plain"]["cell_updates_per_s"], "unit": "cell-updates/s",
+                       "step_cell_updates_per_s": v["fp64_plain"]["step_cell_updates_per_s"],
                        "path": "gf_step_plain: per step, ghost fill into ghosted tiles in HBM, one step launch per "
-                               "level from them, Courant number read back and dt chosen on the host",
-                       "speedup_fp32_fused_over_fp64_plain": cups32 / cupsp},
-        "fp64_fused": {"value": cups64, "unit": "cell-updates/s", "steps": r64["steps"],
-                       "speedup_fp32_over_fp64_fused": cups32 / cups64},
+                               "level from them, Courant number read back and dt chosen on the host; same tag and "
+                               "regrid every 4 steps",
+                       "speedup_fp32_fused_over_fp64_plain": v["speedup_fp32_fused_over_fp64_plain"],
+                       "speedup_step_fp32_fused_over_fp64_plain": v["speedup_step_fp32_fused_over_fp64_plain"]},
+        "fp64_fused": {"value": v["fp64_fused"]["cell_updates_per_s"], "unit": "cell-updates/s",
+                       "speedup_fp32_over_fp64_fused": v["speedup_fp32_over_fp64_fused"]},
         "cpu_baseline": cpu,
-        "wet_cell_fraction_end": r32.get("wet_cell_fraction"),
-        "step_threads": r32.get("step_threads"),
-        "all_wet": wet,
-        "amr_valley": amr,
+        "valley": v,
+        "reservoir_2048": res,
         "ensemble": ens,
         "amr_floodplain": flood,
         "local_time_stepping": ltsc,
+        "learned_tagger": learned,
     }
     print(json.dumps(line))
 

@@ -307,6 +307,13 @@ int gf_set_schedule(gf_ctx *ctx, int32_t workgroups);
  * for on outside 0..3. */
 int gf_profile_enable(gf_ctx *ctx, int32_t on);
 int gf_profile_read(gf_ctx *ctx, int64_t *launches, double *ms_total);
+/* With bit 2 of gf_profile_enable (value 4): an event pair around every
+ * launch of the full-update (step) kernel alone, for the duration of that
+ * kernel by itself.  gf_profile_kernel synchronises and returns the number
+ * of timed launches since the last read and their summed durations in ms.
+ * (The event packets between the dry-patch and step kernels add a few
+ * microseconds to each step.) */
+int gf_profile_kernel(gf_ctx *ctx, int64_t *launches, double *ms_total);
 /* Patch counts over the counted steps (since gf_profile_enable with bit 1):
  * patches that went through the full update, and dry patches found stable
  * (both state buffers already holding the dry update's result, so that
@@ -400,6 +407,15 @@ int gf_run(gf_ctx *ctx, int32_t nsteps, int32_t mode, int32_t check_every, int32
 /* Description of the last failure on this context (static storage, valid
  * until the next call on it). */
 const char *gf_last_error(const gf_ctx *ctx);
+
+/* Achievable HBM bandwidth probe (not a step of the method: the measured
+ * denominator beside the spec-sheet peak of the roofline): one launch of a
+ * grid-stride triad c[i] = a[i] + s b[i] over n floats (16-byte vector
+ * accesses, n a multiple of 4), 12 n bytes moved, on `hip_stream` (NULL: the
+ * null stream).  Device pointers, 16-byte aligned, not overlapping.
+ * Errors: GF_E_INVALID (null or misaligned pointer, n <= 0 or not a multiple
+ * of 4), GF_E_HIP. */
+int gf_probe_triad(const float *a, const float *b, float *c, int64_t n, float s, void *hip_stream);
 
 /* Library version string. */
 const char *gf_version(void);

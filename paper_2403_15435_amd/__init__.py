@@ -63,7 +63,7 @@ NET_FEATURES = 2304
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_initial", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain", "gf_step_lts",
            "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_mass_static", "gf_time", "gf_set_time", "gf_set_step_threads",
-           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
+           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_kernel", "gf_probe_triad", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
            "gf_net_forward", "gf_net_train_step", "gf_net_train_step_dev", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
 
 _lib = None
@@ -114,6 +114,8 @@ def load(path: str = LIB_PATH):
     L.gf_autotune.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(i32), dp]
     L.gf_profile_enable.argtypes = [vp, i32]
     L.gf_profile_read.argtypes = [vp, C.POINTER(i64), dp]
+    L.gf_profile_kernel.argtypes = [vp, C.POINTER(i64), dp]
+    L.gf_probe_triad.argtypes = [vp, vp, vp, i64, C.c_float, vp]
     L.gf_profile_patches.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     i8p = C.POINTER(C.c_int8)
     L.gf_net_set_params.argtypes = [vp, dp, i64]
@@ -133,6 +135,19 @@ def load(path: str = LIB_PATH):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
+
+
+def probe_triad(a, b, c, s: float = 3.0, stream=None):
+    """One launch of the library's HBM triad probe on torch float32 tensors
+    (c = a + s b), on `stream` (default: torch's current stream)."""
+    n = a.numel()
+    if not (b.numel() == n and c.numel() == n):
+        raise ValueError("a, b, c need the same size")
+    L = load()
+    h = stream if stream is not None else _stream_handle()
+    rc = L.gf_probe_triad(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_void_p(c.data_ptr()), n, s, h)
+    if rc != 0:
+        raise GFError(rc, "triad probe launch failed")
 
 
 class GFError(RuntimeError):
@@ -354,10 +369,17 @@ class Context:
         self._chk(self.L.gf_get_step_threads(self._p, C.byref(n)))
         return n.value
 
-    def profile_enable(self, on: bool = True, patches: bool = False):
-        """Time steps with an event pair per stretch of launches (on) and/or
-        have the kernels count patches (patches)."""
-        self._chk(self.L.gf_profile_enable(self._p, (1 if on else 0) | (2 if patches else 0)))
+    def profile_enable(self, on: bool = True, patches: bool = False, kernel: bool = False):
+        """Time steps with an event pair per stretch of launches (on), have the
+        kernels count patches (patches), time each step-kernel launch alone
+        with its own event pair (kernel)."""
+        self._chk(self.L.gf_profile_enable(self._p, (1 if on else 0) | (2 if patches else 0) | (4 if kernel else 0)))
+
+    def profile_kernel(self):
+        """(timed step-kernel launches, their summed ms) since the last read."""
+        n, ms = C.c_int64(), C.c_double()
+        self._chk(self.L.gf_profile_kernel(self._p, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
     def profile_read(self):
         n, ms = C.c_int64(), C.c_double()

@@ -21,6 +21,7 @@ UNITS = [
     ("gf_kernels_f64.hip", ["-ffp-contract=off"]),
     ("gf_net.hip", ["-ffp-contract=off"]),
     ("gf_static.hip", ["-ffp-contract=off"]),
+    ("gf_probe.hip", ["-ffp-contract=off"]),
     ("gf_host.cpp", ["-ffp-contract=off", "-pthread"]),
 ]
 

@@ -234,6 +234,10 @@ struct gf_ctx {
     std::vector<hipEvent_t> ev;
     int64_t prof_launches = 0;
     double prof_ms = 0.0;
+    // prof_kernel: an event pair around every step-kernel launch alone
+    bool prof_kernel = false;
+    std::vector<hipEvent_t> kev;     // start, stop of pair i at 2i, 2i + 1
+    int64_t kev_n = 0;
     std::string err;
     // learned tagger
     struct Net {
@@ -806,6 +810,22 @@ int launch_reflux(gf_ctx *c, int lts = 0, int tick = 0)
     return GF_OK;
 }
 
+// start (which 0) or stop (1) event of the step-kernel launch being issued,
+// when the step kernel is timed alone
+int kernel_event(gf_ctx *c, int mode, int which)
+{
+    if (!c->prof_kernel || mode != 0) return GF_OK;
+    const size_t need = 2 * (size_t)c->kev_n + 2;
+    while (c->kev.size() < need) {
+        hipEvent_t x;
+        HIPCHK(c, hipEventCreate(&x));
+        c->kev.push_back(x);
+    }
+    HIPCHK(c, hipEventRecord(c->kev[2 * (size_t)c->kev_n + (size_t)which], c->stream));
+    if (which == 1) c->kev_n++;
+    return GF_OK;
+}
+
 int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0, int n_listed = -1)
 {
     const int n = (int)c->desc.size();
@@ -851,6 +871,8 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         e = n_listed >= 0 ? hipMemsetD32Async((hipDeviceptr_t)c->d_wet_count, n_listed, 1, c->stream)
                           : gf_launch_dry_f32(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
+        int rc = kernel_event(c, mode, 0);
+        if (rc) return rc;
         e = gf_launch_step_f32(a, c->m, c->step_threads, grid, c->stream);
     } else {
         StepArgs<double> a{};
@@ -861,9 +883,15 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         e = n_listed >= 0 ? hipMemsetD32Async((hipDeviceptr_t)c->d_wet_count, n_listed, 1, c->stream)
                           : gf_launch_dry_f64(a, c->m, c->stream);
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
+        int rc = kernel_event(c, mode, 0);
+        if (rc) return rc;
         e = gf_launch_step_f64(a, c->m, c->step_threads, grid, c->stream);
     }
     if (e != hipSuccess) return fail(c, GF_E_HIP, "step launch: %s", hipGetErrorString(e));
+    {
+        int rc = kernel_event(c, mode, 1);
+        if (rc) return rc;
+    }
     if (timed) c->prof_launches++;
     // level l ends its step at tick k when 2^(L1 - l) divides k + 1, and only
     // levels below the finest have reflux tasks: none end where k + 1 is odd
@@ -1291,6 +1319,7 @@ void gf_destroy(gf_ctx *c)
     for (void *p : pn)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -2733,7 +2762,7 @@ int gf_profile_patches(gf_ctx *c, int64_t *full_updates, int64_t *stable_dry)
 
 int gf_profile_enable(gf_ctx *c, int32_t on)
 {
-    if (!c || on < 0 || on > 3) return GF_E_INVALID;
+    if (!c || on < 0 || on > 7) return GF_E_INVALID;
     if (c->prof_open) {
         int rc = prof_mark_end(c);
         if (rc) return rc;
@@ -2748,6 +2777,24 @@ int gf_profile_enable(gf_ctx *c, int32_t on)
     if ((on & 2) && !c->prof_stats) HIPCHK(c, hipMemsetAsync(c->d_stats, 0, 8 * 8 * 65, c->stream));
     c->prof = (on & 1) != 0;
     c->prof_stats = (on & 2) != 0;
+    if ((on & 4) && !c->prof_kernel) c->kev_n = 0;
+    c->prof_kernel = (on & 4) != 0;
+    return GF_OK;
+}
+
+int gf_profile_kernel(gf_ctx *c, int64_t *launches, double *ms_total)
+{
+    if (!c) return GF_E_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (int64_t i = 0; i < c->kev_n; ++i) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->kev[2 * (size_t)i], c->kev[2 * (size_t)i + 1]));
+        sum += ms;
+    }
+    if (launches) *launches = c->kev_n;
+    if (ms_total) *ms_total = sum;
+    c->kev_n = 0;
     return GF_OK;
 }
 

@@ -95,3 +95,75 @@ def check_fp32(sc, leaves, g, o, level):
     rel = np.abs(Hg - Ho)[away] / Ho[away] if away.any() else np.zeros(1)
     front = np.abs(Hg - Ho)[near] if near.any() else np.zeros(1)
     return float(rel.max()), float(front.max())
+
+
+def oracle_refine_passes(o, sc, passes, precision="f64"):
+    """The oracle's counterpart of gf_set_initial with refinement passes: the
+    recipe on every leaf, then up to `passes` rounds of plain tagging,
+    regridding and the recipe again (stopping when nothing is flagged)."""
+    init_oracle(o, sc, precision)
+    for _ in range(passes):
+        f = o.tag()
+        if not f.any():
+            break
+        o.regrid(f)
+        init_oracle(o, sc, precision)
+
+
+def _dilate_sep(mask, r):
+    """Chebyshev dilation by r cells, as a row pass then a column pass."""
+    out = mask.copy()
+    for d in range(1, r + 1):
+        out[:, d:] |= mask[:, :-d]
+        out[:, :-d] |= mask[:, d:]
+    tmp = out.copy()
+    for d in range(1, r + 1):
+        out[d:, :] |= tmp[:-d, :]
+        out[:-d, :] |= tmp[d:, :]
+    return out
+
+
+def check_fp32_large(sc, leaves, g, o, finest):
+    """check_fp32 for meshes too large to project onto the finest level with
+    per-level dilations: the same bar and front rule (a cell is at a front
+    when a cell of depth <= 1e-2 m in either solution lies within 2 cells of
+    the cell's own level), with a finer cell counted at a coarser level
+    through its parent (any shallow child makes the parent shallow: at least
+    as many front cells as the exact rule).  Returns (max relative h error
+    away from fronts, max absolute error at fronts, cells away, cells at
+    fronts)."""
+    lv = np.asarray(leaves)
+    m = sc.m
+    L = int(finest)
+    S = np.zeros((sc.mj * m << L, sc.mi * m << L), dtype=bool)
+
+    def origin(t, l, ix, iy):
+        return (t // sc.mi) * (1 << l) + iy, (t % sc.mi) * (1 << l) + ix
+    for k, (t, l, ix, iy) in enumerate(lv):
+        sh = (o[k, 0] <= 1e-2) | (g[k, 0] <= 1e-2)
+        if not sh.any():
+            continue
+        PJ, PI = origin(t, l, ix, iy)
+        r = 1 << (L - l)
+        S[PJ * m * r:(PJ + 1) * m * r, PI * m * r:(PI + 1) * m * r] = np.repeat(np.repeat(sh, r, 0), r, 1)
+    near = {}
+    levels = sorted(set(int(l) for l in lv[:, 1]), reverse=True)
+    cur, cl = S, L
+    for l in range(L, min(levels) - 1, -1):
+        if l < cl:
+            cur = cur.reshape(cur.shape[0] // 2, 2, cur.shape[1] // 2, 2).any(axis=(1, 3))
+            cl = l
+        if l in levels:
+            near[l] = _dilate_sep(cur, 2)
+    rel, front, n_away, n_front = 0.0, 0.0, 0, 0
+    for k, (t, l, ix, iy) in enumerate(lv):
+        PJ, PI = origin(t, l, ix, iy)
+        nm = near[int(l)][PJ * m:(PJ + 1) * m, PI * m:(PI + 1) * m]
+        d = np.abs(g[k, 0] - o[k, 0])
+        if (~nm).any():
+            rel = max(rel, float((d[~nm] / o[k, 0][~nm]).max()))
+            n_away += int((~nm).sum())
+        if nm.any():
+            front = max(front, float(d[nm].max()))
+            n_front += int(nm.sum())
+    return rel, front, n_away, n_front

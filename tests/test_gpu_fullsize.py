@@ -5,15 +5,16 @@ times (512-thread step kernel on the resident persistent grid):
   against the CPU oracle over 10 steps of the oracle's lengths;
 - the 256-scenario ensemble in one launch: sampled scenarios bit for bit
   against their own oracle runs;
-- the 25k-leaf AMR valley, too large for the oracle: properties that hold
-  at any size (fused and plain paths equal bit for bit through a regrid,
-  the volume budget closed)."""
+- the 25k-leaf AMR valley (levels 0-6): against the oracle (OpenMP over
+  leaves) bit for bit in FP64 and within the FP32 bars, from the mesh each
+  side builds by refinement passes, through 4 steps, a tag and regrid, and
+  4 more steps; and fused against plain through a regrid."""
 import numpy as np
 import pytest
 
 import paper_2403_15435_amd as gf
 from paper_2403_15435_amd import inputs
-from helpers import _dilate, init_oracle, to_finest
+from helpers import _dilate, check_fp32_large, init_oracle, oracle_refine_passes, to_finest
 
 pytestmark = pytest.mark.gpu
 
@@ -230,3 +231,60 @@ def test_reservoir_2048_late_in_the_run(prec):
     assert a.time(0) == b.time(0)
     assert np.array_equal(a.state(0), b.state(0))
     assert np.array_equal(M, b.mass(0))
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_valley_25k_leaves_against_oracle(orc, prec):
+    """The AMR valley at its full size (the workload of the headline
+    benchmark): each side builds its mesh from level 0 by plain-tagger
+    passes over the initial flood (gf_set_initial on the GPU), then both take
+    4 steps from t = 4000 s on the hydrograph plateau with the oracle's step
+    lengths, tag, regrid, and take 4 more.  FP64: leaves, flags and state
+    equal bit for bit, the budget (inflow and outflow included) closed to
+    1e-12.  FP32 (oracle on the rounded bed and the FP32-formed state): the
+    leaves and flags equal, h within 2e-5 relative beyond 2 cells of a cell of
+    depth <= 1e-2 m and 1e-3 m within."""
+    f32 = prec == gf.GF_FP32
+    ps = "f32" if f32 else "f64"
+    sc = inputs.v_valley()
+    passes = sc.max_level - sc.min_level
+    o = orc.Oracle(sc)
+    if f32:
+        o.set_bathy_f32(True)
+    oracle_refine_passes(o, sc, passes, ps)
+    print(f"valley ({ps}): oracle mesh {o.n_leaves} leaves, {orc.threads()} threads", flush=True)
+    ctx = gf.Context([sc], precision=prec, max_patches=40000)
+    _bench_shape(ctx)
+    ctx.set_initial(0, max_passes=passes)
+    assert np.array_equal(ctx.leaves(0), o.leaves())
+    assert o.n_leaves > 20000
+    r0 = o.state()
+    assert np.array_equal(ctx.state(0), r0)
+    del r0
+    o.set_time(4000.0, 0.0)
+    ctx.set_time(0, 4000.0, 0.0)
+    m0 = o.mass()[0]
+    _, dts = o.advance(4, return_dt=True)
+    ctx.step(len(dts), dts)
+    fo = o.tag()
+    fg = ctx.tag()
+    assert np.array_equal(fo, fg)
+    o.regrid(fo)
+    ctx.regrid(None)
+    assert np.array_equal(ctx.leaves(0), o.leaves())
+    _, dts2 = o.advance(4, return_dt=True)
+    ctx.step(len(dts2), dts2)
+    g, r = ctx.state(0), o.state()
+    M = ctx.mass(0)
+    print(f"valley ({ps}): 8 steps to t = {o.t:.3f} s, {o.n_leaves} leaves after the regrid, "
+          f"{int((fo != 0).sum())} flags set", flush=True)
+    if not f32:
+        assert np.array_equal(g[:, :3], r[:, :3])
+        Mo = o.mass()
+        assert np.array_equal(M, Mo) or np.allclose(M, Mo, rtol=0, atol=1e-12 * M[0])
+        assert abs(M[0] - m0 - M[1] - M[2]) <= 1e-12 * M[0]
+        return
+    rel, front, n_away, n_front = check_fp32_large(sc, o.leaves(), g, r, sc.max_level)
+    print(f"valley fp32: max rel h err away from fronts {rel:.2e} (bar 2e-5) over {n_away} cells, at fronts "
+          f"{front:.2e} m (bar 1e-3) over {n_front} cells", flush=True)
+    assert rel <= 2e-5 and front <= 1e-3
