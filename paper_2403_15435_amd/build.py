@@ -17,7 +17,7 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall", "-Wno
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 UNITS = [
-    ("gf_kernels_f32.hip", ["-ffp-contract=fast"]),
+    ("gf_kernels_f32.hip", ["-ffp-contract=on"]),
     ("gf_kernels_f64.hip", ["-ffp-contract=off"]),
     ("gf_net.hip", ["-ffp-contract=off"]),
     ("gf_static.hip", ["-ffp-contract=off"]),

@@ -848,7 +848,7 @@ def test_profile_window_counts_steps_and_fits_the_wall_clock():
     assert ctx.profile_read() == (0, 0.0)
     ctx.profile_enable(False)
     with pytest.raises(gf.GFError):
-        ctx._chk(ctx.L.gf_profile_enable(ctx._p, 4))
+        ctx._chk(ctx.L.gf_profile_enable(ctx._p, 8))
 
 
 def test_patch_pool_exhaustion_is_refused_cleanly():
