@@ -248,6 +248,58 @@ def _finest_depth(sc, leaves, st, level):
     return out
 
 
+def _dilated_flags(sc, lv, fl):
+    """Plain flags with every refine request spread to the neighbouring leaves
+    (faces and corners) that are as coarse or coarser: a trivial anticipating
+    tagger, the baseline the network has to beat."""
+    lv = np.asarray(lv)
+    pos = {(int(l), int(ix), int(iy)): k for k, (t, l, ix, iy) in enumerate(lv)}
+    out = np.asarray(fl, np.int8).copy()
+    for k in np.flatnonzero(np.asarray(fl) > 0):
+        t, l, ix, iy = (int(v) for v in lv[k])
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                X, Y = ix + dx, iy + dy
+                if not (0 <= X < (1 << l) and 0 <= Y < (1 << l)):
+                    continue
+                for a in range(l, -1, -1):
+                    j = pos.get((a, X >> (l - a), Y >> (l - a)))
+                    if j is not None:
+                        if lv[j, 1] < sc.max_level:
+                            out[j] = 1
+                        break
+    return out
+
+
+class _RunStats:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def _dilated_run(ctx, sc, nsteps, check=4, regrid_every=16):
+    """The plain tagger every regrid_every steps with its refine requests
+    dilated by one leaf; misses counted at the checks between (no regrid),
+    as gf_run's sparse mode counts them."""
+    st = _RunStats(steps=0, regrids=0, forced_regrids=0, checks=0, misses=0, leaf_steps=0, seconds=0.0)
+    _sync()
+    t0 = time.perf_counter()
+    for k in range(0, nsteps, check):
+        fl = ctx.tag()
+        if k % regrid_every == 0:
+            ctx.regrid(_dilated_flags(sc, ctx.leaves(0), fl))
+            st.regrids += 1
+        else:
+            st.checks += fl.size
+            st.misses += int((fl > 0).sum())
+        ns = min(check, nsteps - k)
+        ctx.step(ns)
+        st.steps += ns
+        st.leaf_steps += ctx.leaves(0).shape[0] * ns
+    _sync()
+    st.seconds = time.perf_counter() - t0
+    return st
+
+
 def learned_tagger(n_train=50, n_eval=10, steps=2000, window=16, check=4, iters=400, batch=256):
     """The learned tagger on the reservoir geometry as AMR: 10 km square,
     levels 0-6 of 32 x 32 patches (finest 4.88 m), reservoir r = 400 m with
@@ -291,27 +343,43 @@ def learned_tagger(n_train=50, n_eval=10, steps=2000, window=16, check=4, iters=
     cw = counts.sum() / (3.0 * np.maximum(counts, 1))
     sc, ctx = make(5001)
     ctx.net_set_params(inputs.cnn_init_params(0))
+    # the training set on the device once (bfloat16 features, int8 labels);
+    # each step trains on a batch gathered there (gf_net_train_step_dev), the
+    # loss read back every 10 steps
+    import torch
+    Xt = torch.from_numpy(X.reshape(Y.size, -1)).to("cuda").to(torch.bfloat16).view(torch.int16)
+    Yt = torch.from_numpy(Y.astype(np.int8)).to("cuda")
     losses = []
+    _sync()
     t1 = time.perf_counter()
-    for _ in range(iters):
-        idx = rng.choice(Y.size, size=min(batch, Y.size), replace=False)
-        losses.append(ctx.net_train_step(X[idx].astype(np.float64), Y[idx], cw, lr=3e-3))
+    for it in range(iters):
+        idx = torch.from_numpy(rng.choice(Y.size, size=min(batch, Y.size), replace=False)).to("cuda")
+        xb, yb = Xt.index_select(0, idx).contiguous(), Yt.index_select(0, idx).contiguous()
+        want = it % 10 == 9 or it < 10 or it >= iters - 10
+        loss = ctx.net_train_step_dev(xb, yb, cw, lr=3e-3, want_loss=want)
+        if want:
+            losses.append(loss)
     _sync()
     t_train = time.perf_counter() - t1
     params = ctx.net_params()
     ctx.close()
     print(f"[bench] learned: trained on {Y.size} samples {counts.tolist()}, loss {np.mean(losses[:10]):.3f} -> "
           f"{np.mean(losses[-10:]):.3f}", file=sys.stderr, flush=True)
-    names = {gf.GF_RUN_PLAIN: "plain_every_4", gf.GF_RUN_SPARSE: "plain_every_16", gf.GF_RUN_LEARNED: "learned_every_16"}
+    names = {gf.GF_RUN_PLAIN: "plain_every_4", gf.GF_RUN_SPARSE: "plain_every_16", gf.GF_RUN_LEARNED: "learned_every_16",
+             "dilated": "plain_dilated_every_16"}
     acc = {v: {"regrids": 0, "forced_regrids": 0, "checks": 0, "misses": 0, "leaf_steps": 0, "seconds": 0.0,
-               "max_abs_dh_vs_plain": [], "budget_residual_rel": []} for v in names.values()}
+               "max_abs_dh_vs_plain": [], "mean_abs_dh_wet": [], "frac_dh_over_10cm": [], "budget_residual_rel": []}
+           for v in names.values()}
     for j in range(n_eval):
         hp = None
-        for mode in (gf.GF_RUN_PLAIN, gf.GF_RUN_SPARSE, gf.GF_RUN_LEARNED):
+        for mode in (gf.GF_RUN_PLAIN, gf.GF_RUN_SPARSE, gf.GF_RUN_LEARNED, "dilated"):
             sc, c2 = make(5051 + j)
             c2.net_set_params(params)
             m0 = c2.mass(0)
-            st = c2.run(steps, mode, check, window)
+            if mode == "dilated":
+                st = _dilated_run(c2, sc, steps, check, window)
+            else:
+                st = c2.run(steps, mode, check, window)
             M = c2.mass(0)
             h = _finest_depth(sc, c2.leaves(0), c2.state(0), sc.max_level)
             hp = h if mode == gf.GF_RUN_PLAIN else hp
@@ -319,7 +387,11 @@ def learned_tagger(n_train=50, n_eval=10, steps=2000, window=16, check=4, iters=
             for k in ("regrids", "forced_regrids", "checks", "misses", "leaf_steps"):
                 a[k] += int(getattr(st, k))
             a["seconds"] += st.seconds
-            a["max_abs_dh_vs_plain"].append(float(np.abs(h - hp).max()))
+            d = np.abs(h - hp)
+            wet = (h > 1e-2) | (hp > 1e-2)
+            a["max_abs_dh_vs_plain"].append(float(d.max()))
+            a["mean_abs_dh_wet"].append(float(d[wet].mean()) if wet.any() else 0.0)
+            a["frac_dh_over_10cm"].append(float(np.count_nonzero(d[wet] > 0.1)) / max(int(wet.sum()), 1))
             a["budget_residual_rel"].append(float(abs((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) / m0[0]))
             c2.close()
         print(f"[bench] learned: evaluated seed {5051 + j}", file=sys.stderr, flush=True)
@@ -327,6 +399,8 @@ def learned_tagger(n_train=50, n_eval=10, steps=2000, window=16, check=4, iters=
         a["miss_rate"] = a["misses"] / max(a["checks"], 1)
         d = a.pop("max_abs_dh_vs_plain")
         a["max_abs_dh_vs_plain_m"] = {"max": max(d), "median": float(np.median(d))}
+        a["mean_abs_dh_wet_vs_plain_m"] = float(np.mean(a.pop("mean_abs_dh_wet")))
+        a["frac_wet_cells_dh_over_10cm"] = float(np.mean(a.pop("frac_dh_over_10cm")))
         a["budget_residual_rel_max"] = max(a.pop("budget_residual_rel"))
     return {"workload": "reservoir geometry as AMR: 10 km fractal terrain, levels 0-6 of 32x32 patches, reservoir "
                         "h=20 m r=400 m at a seeded centre, n=0.033; FP32",

@@ -13,6 +13,7 @@
 namespace gfnet {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t to_bf16(float x)
@@ -25,21 +26,33 @@ __device__ __forceinline__ uint16_t to_bf16(float x)
 
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// One 16 x 16 output tile: acc += A (16 x K) B (K x 16), K a multiple of 16.
-// Lane l supplies A(l % 16, k0 + 4 (l / 16) + j) and B(k0 + 4 (l / 16) + j, l % 16)
-// for j < 4, and holds C(4 (l / 16) + r, l % 16) for r < 4: the operand layout of
-// the 16x16x16 bf16 matrix instruction.
+// One 16 x 16 output tile: acc += A (16 x K) B (K x 16), K a multiple of 16,
+// on gfx950's 16x16x32 bf16 matrix instruction, with one 16x16x16 step for
+// a 16-wide remainder.  16x16x32: lane l supplies A(l % 16, k0 + 8 (l / 16) + j)
+// and B(k0 + 8 (l / 16) + j, l % 16) for j < 8; 16x16x16: the same with 4
+// values from k0 + 4 (l / 16).  Either way lane l holds C(4 (l / 16) + r, l % 16)
+// for r < 4.
 template <class FA, class FB>
 __device__ __forceinline__ f32x4 mma_tile(int K, FA fa, FB fb, f32x4 acc)
 {
     const int lane = threadIdx.x & 63;
-    const int i = lane & 15, kq = (lane >> 4) * 4;
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    const int i = lane & 15, g = lane >> 4;
+    int k0 = 0;
+    for (; k0 + 32 <= K; k0 += 32) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            av[j] = __builtin_bit_cast(__bf16, (uint16_t)fa(i, k0 + 8 * g + j));
+            bv[j] = __builtin_bit_cast(__bf16, (uint16_t)fb(k0 + 8 * g + j, i));
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    if (k0 < K) {
         bf16x4 av, bv;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            av[j] = (short)fa(i, k0 + kq + j);
-            bv[j] = (short)fb(k0 + kq + j, i);
+            av[j] = (short)fa(i, k0 + 4 * g + j);
+            bv[j] = (short)fb(k0 + 4 * g + j, i);
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
     }
