@@ -276,17 +276,28 @@ int gf_set_time(gf_ctx *ctx, int32_t scen, double t, double dt_next);
  * Errors: GF_E_UNSUPPORTED for a size that is not built. */
 int gf_set_step_threads(gf_ctx *ctx, int32_t nt);
 int gf_get_step_threads(gf_ctx *ctx, int32_t *nt);
-/* Autotuner: time every built step-kernel shape (workgroup size x schedule)
- * for `steps` steps on the context's current state, keep the fastest, and
- * restore the state, clocks and budgets after each trial, so the simulation
- * is unchanged.  cache_path (nullable; NULL takes gf_config.autotune_cache,
- * which may be NULL too): a text file of earlier choices keyed
- * by GPU architecture, precision, patch size and patch count (rounded up to a
- * power of two); a hit skips the timing (us_per_step is then -1), a miss
- * appends the new choice.  Outputs are nullable.
+/* LDS row padding of the step kernel's tile (0 or 1 extra words per row of
+ * m+4 cells): a shape the tuner chooses; results do not depend on it.
+ * Errors: GF_E_UNSUPPORTED for other values. */
+int gf_set_step_pad(gf_ctx *ctx, int32_t pad);
+/* Autotuner: time every built step-kernel shape for `steps` steps on the
+ * context's current state, keep the fastest, and restore the state, clocks
+ * and budgets after each trial, so the simulation is unchanged.  Shapes:
+ * workgroup size (m = 32: 256, 512, 1024 threads, i.e. 4, 2, 1 cells per
+ * thread; m = 16: 64, 128, 256) x LDS row padding (0, 1) x schedule (the
+ * resident persistent grid, half of it, one workgroup per patch): 18.
+ * cache_path (nullable; NULL takes gf_config.autotune_cache, which may be
+ * NULL too): a text file of earlier choices keyed by GPU architecture,
+ * precision, patch size and patch count (rounded up to a power of two); a
+ * hit skips the timing (us_per_step is then -1), a miss appends the new
+ * choice.  Outputs are nullable.
  * Errors: GF_E_INVALID, GF_E_STATE (no bathymetry or leaves), GF_E_HIP. */
 int gf_autotune(gf_ctx *ctx, int32_t steps, const char *cache_path, int32_t *threads, int32_t *schedule,
-                double *us_per_step);
+                int32_t *pad, double *us_per_step);
+/* The last timed gf_autotune's trials: n rows of (threads, schedule,
+ * padding) into shapes (n x 3, nullable) and their us per step into us
+ * (nullable); *n receives the count.  Errors: GF_E_INVALID (cap < n). */
+int gf_autotune_trials(gf_ctx *ctx, int32_t *shapes, double *us, int64_t cap, int64_t *n);
 
 /* Schedule of the step kernel.  workgroups = -1 (default): as many
  * persistent workgroups as the GPU holds at once, each taking patches of

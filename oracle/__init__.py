@@ -28,7 +28,12 @@ _ip = C.POINTER(C.c_int)
 # forms of one step.  "per_edge": the transverse solver splits each edge's
 # increment into the neighbouring cell separately (the form as first written
 # in the cited CTU method) instead of the cell's net normal increment.
-VARIANTS = {None: [], "per_edge": ["-DORC_TRANSVERSE_PER_EDGE"]}
+# "asan": AddressSanitizer and UndefinedBehaviorSanitizer, every report
+# fatal; loaded only by a process started with the sanitizer runtime
+# preloaded (a check of the oracle itself, not of the method).
+VARIANTS = {None: [], "per_edge": ["-DORC_TRANSVERSE_PER_EDGE"],
+            "asan": ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                     "-fno-sanitize-recover=all"]}
 
 
 def _lib_path(variant=None) -> str:

@@ -63,7 +63,7 @@ NET_FEATURES = 2304
 EXPORTS = ["gf_create", "gf_destroy", "gf_set_bathymetry", "gf_set_initial", "gf_set_leaves", "gf_get_leaves", "gf_set_patch",
            "gf_get_patch", "gf_set_state", "gf_get_state", "gf_fill_ghosts", "gf_get_ghosted", "gf_step", "gf_step_plain", "gf_step_lts",
            "gf_tag", "gf_regrid", "gf_set_gauges", "gf_get_gauges", "gf_mass", "gf_mass_static", "gf_time", "gf_set_time", "gf_set_step_threads",
-           "gf_get_step_threads", "gf_set_schedule", "gf_autotune", "gf_profile_enable", "gf_profile_read", "gf_profile_kernel", "gf_probe_triad", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
+           "gf_get_step_threads", "gf_set_step_pad", "gf_set_schedule", "gf_autotune", "gf_autotune_trials", "gf_profile_enable", "gf_profile_read", "gf_profile_kernel", "gf_probe_triad", "gf_profile_patches", "gf_net_set_params", "gf_net_get_params", "gf_net_features",
            "gf_net_forward", "gf_net_train_step", "gf_net_train_step_dev", "gf_net_predict", "gf_net_collect", "gf_run", "gf_last_error", "gf_version"]
 
 _lib = None
@@ -111,7 +111,9 @@ def load(path: str = LIB_PATH):
     L.gf_set_step_threads.argtypes = [vp, i32]
     L.gf_get_step_threads.argtypes = [vp, C.POINTER(i32)]
     L.gf_set_schedule.argtypes = [vp, i32]
-    L.gf_autotune.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(i32), dp]
+    L.gf_autotune.argtypes = [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), dp]
+    L.gf_autotune_trials.argtypes = [vp, C.POINTER(i32), dp, i64, C.POINTER(i64)]
+    L.gf_set_step_pad.argtypes = [vp, i32]
     L.gf_profile_enable.argtypes = [vp, i32]
     L.gf_profile_read.argtypes = [vp, C.POINTER(i64), dp]
     L.gf_profile_kernel.argtypes = [vp, C.POINTER(i64), dp]
@@ -357,12 +359,31 @@ class Context:
         self._chk(self.L.gf_set_schedule(self._p, int(workgroups)))
 
     def autotune(self, steps: int = 5, cache: Optional[str] = None):
-        """Time the step kernel's launch shapes on the current state and keep
-        the fastest (state unchanged).  Returns (threads, schedule, us_per_step)."""
-        nt, sc, us = C.c_int32(), C.c_int32(), C.c_double()
+        """Time the step kernel's shapes on the current state and keep the
+        fastest (state unchanged).  Returns (threads, schedule, us_per_step);
+        the padding chosen is in autotune_choice()."""
+        nt, sc, pad, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         self._chk(self.L.gf_autotune(self._p, steps, cache.encode() if cache else None,
-                                     C.byref(nt), C.byref(sc), C.byref(us)))
+                                     C.byref(nt), C.byref(sc), C.byref(pad), C.byref(us)))
+        self._tuned = (nt.value, sc.value, pad.value, us.value)
         return nt.value, sc.value, us.value
+
+    def autotune_choice(self):
+        """(threads, schedule, padding, us_per_step) of the last autotune."""
+        return getattr(self, "_tuned", None)
+
+    def autotune_trials(self):
+        """The last timed autotune's trials: rows (threads, schedule, padding, us per step)."""
+        n = C.c_int64()
+        self._chk(self.L.gf_autotune_trials(self._p, None, None, 0, C.byref(n)))
+        sh = np.zeros((max(n.value, 1), 3), dtype=np.int32)
+        us = np.zeros(max(n.value, 1))
+        self._chk(self.L.gf_autotune_trials(self._p, sh.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(us), n.value,
+                                            C.byref(n)))
+        return [(int(a), int(b), int(c), float(u)) for (a, b, c), u in zip(sh[:n.value], us[:n.value])]
+
+    def set_step_pad(self, pad: int):
+        self._chk(self.L.gf_set_step_pad(self._p, pad))
 
     def step_threads(self) -> int:
         n = C.c_int32()

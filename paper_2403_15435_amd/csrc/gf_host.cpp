@@ -156,7 +156,10 @@ struct gf_ctx {
     int m = 32;
     int step_threads = 256;   // workgroup size of the step kernel
     int sched_wg = -1;        // step workgroups: 0 one per patch, > 0 that many persistent, -1 the resident count
-    int resident[3] = {0, 0, 0}; // resident workgroup count per step-thread choice (cached)
+    int step_pad = 0;         // LDS words of padding per tile row of the step kernel
+    int resident[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // resident workgroups per (threads, padding) (cached)
+    struct Trial { int32_t nt, sched, pad; double us; };
+    std::vector<Trial> tune_trials;  // the last gf_autotune's timings
     uint8_t *dry[2] = {nullptr, nullptr};   // per slot and buffer: all interior cells dry
     uint8_t *d_dstab = nullptr;              // per slot: dry-update state (unknown / last read buffer / stable)
     unsigned long long *d_stats = nullptr;   // patches through the step kernel, stable dry patches
@@ -841,10 +844,11 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         if (want < 0) {
             const int base = c->m == 16 ? 64 : 256;
             const int ki = c->step_threads == base ? 0 : (c->step_threads == 2 * base ? 1 : 2);
-            if (c->resident[ki] <= 0)
-                c->resident[ki] = c->prec == GF_FP32 ? gf_step_resident_f32(c->m, c->step_threads)
-                                                     : gf_step_resident_f64(c->m, c->step_threads);
-            want = c->resident[ki];
+            int &res = c->resident[ki][c->step_pad];
+            if (res <= 0)
+                res = c->prec == GF_FP32 ? gf_step_resident_f32(c->m, c->step_threads, c->step_pad)
+                                         : gf_step_resident_f64(c->m, c->step_threads, c->step_pad);
+            want = res;
         }
         if (want > 0 && want < n) grid = want;
     }
@@ -873,7 +877,7 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         int rc = kernel_event(c, mode, 0);
         if (rc) return rc;
-        e = gf_launch_step_f32(a, c->m, c->step_threads, grid, c->stream);
+        e = gf_launch_step_f32(a, c->m, c->step_threads, c->step_pad, grid, c->stream);
     } else {
         StepArgs<double> a{};
         fill_step_args<double>(c, a, dt_fixed, mode, c->cfg.dry_tol);
@@ -885,7 +889,7 @@ int launch_step(gf_ctx *c, double dt_fixed, int mode, int lts = 0, int tick = 0,
         if (e != hipSuccess) return fail(c, GF_E_HIP, "dry launch: %s", hipGetErrorString(e));
         int rc = kernel_event(c, mode, 0);
         if (rc) return rc;
-        e = gf_launch_step_f64(a, c->m, c->step_threads, grid, c->stream);
+        e = gf_launch_step_f64(a, c->m, c->step_threads, c->step_pad, grid, c->stream);
     }
     if (e != hipSuccess) return fail(c, GF_E_HIP, "step launch: %s", hipGetErrorString(e));
     {
@@ -2556,6 +2560,28 @@ int gf_set_schedule(gf_ctx *c, int32_t workgroups)
     return GF_OK;
 }
 
+int gf_set_step_pad(gf_ctx *c, int32_t pad)
+{
+    if (!c) return GF_E_INVALID;
+    if (pad < 0 || pad > 1) return fail(c, GF_E_UNSUPPORTED, "no step kernel built with %d words of row padding", pad);
+    c->step_pad = pad;
+    return GF_OK;
+}
+
+int gf_autotune_trials(gf_ctx *c, int32_t *shapes, double *us, int64_t cap, int64_t *n)
+{
+    if (!c) return GF_E_INVALID;
+    if (n) *n = (int64_t)c->tune_trials.size();
+    if (!shapes && !us) return GF_OK;
+    if (cap < (int64_t)c->tune_trials.size()) return fail(c, GF_E_INVALID, "trial buffer too small");
+    for (size_t k = 0; k < c->tune_trials.size(); ++k) {
+        const auto &t = c->tune_trials[k];
+        if (shapes) { shapes[3 * k] = t.nt; shapes[3 * k + 1] = t.sched; shapes[3 * k + 2] = t.pad; }
+        if (us) us[k] = t.us;
+    }
+    return GF_OK;
+}
+
 int gf_get_step_threads(gf_ctx *c, int32_t *nt)
 {
     if (!c || !nt) return GF_E_INVALID;
@@ -2571,27 +2597,30 @@ int gf_get_step_threads(gf_ctx *c, int32_t *nt)
 namespace {
 
 // cache file: one line per key, "key threads sched us_per_step"
-bool cache_lookup(const char *path, const std::string &key, int *nt, int *sched)
+// cache lines: key threads schedule padding us_per_step
+bool cache_lookup(const char *path, const std::string &key, int *nt, int *sched, int *pad)
 {
     if (!path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
-    char k[200];
-    int a = 0, b = 0;
+    char line[512], k[200];
+    int a = 0, b = 0, d = 0;
     double us = 0.0;
     bool found = false;
-    while (fscanf(f, "%199s %d %d %lf", k, &a, &b, &us) == 4)
-        if (key == k) { *nt = a; *sched = b; found = true; }
+    while (fgets(line, sizeof line, f))
+        if (sscanf(line, "%199s %d %d %d %lf", k, &a, &b, &d, &us) == 5 && key == k) {
+            *nt = a; *sched = b; *pad = d; found = true;
+        }
     fclose(f);
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, int nt, int sched, double us)
+void cache_store(const char *path, const std::string &key, int nt, int sched, int pad, double us)
 {
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %.3f\n", key.c_str(), nt, sched, us);
+    fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), nt, sched, pad, us);
     fclose(f);
 }
 
@@ -2646,7 +2675,7 @@ int gf_get_gauges(gf_ctx *c, int32_t g, double *out, int64_t cap_out, int64_t *n
 }
 
 int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threads_out, int32_t *sched_out,
-                double *us_per_step_out)
+                int32_t *pad_out, double *us_per_step_out)
 {
     if (!c || steps <= 0) return GF_E_INVALID;
     for (auto &s : c->sc)
@@ -2655,14 +2684,17 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
     if (rc) return rc;
     const TuneKey key = tune_key(c);
     if (!cache_path && !c->tune_cache.empty()) cache_path = c->tune_cache.c_str();
-    int best_nt = c->step_threads, best_sched = c->sched_wg;
+    int best_nt = c->step_threads, best_sched = c->sched_wg, best_pad = c->step_pad;
     double best_us = -1.0;
-    if (cache_lookup(cache_path, key.text, &best_nt, &best_sched)) {
+    if (cache_lookup(cache_path, key.text, &best_nt, &best_sched, &best_pad)) {
+        if (best_pad < 0 || best_pad > 1 || best_sched < -1) return fail(c, GF_E_INVALID, "bad autotune cache entry");
         rc = gf_set_step_threads(c, best_nt);
         if (rc) return rc;
         c->sched_wg = best_sched;
+        c->step_pad = best_pad;
         if (threads_out) *threads_out = best_nt;
         if (sched_out) *sched_out = best_sched;
+        if (pad_out) *pad_out = best_pad;
         if (us_per_step_out) *us_per_step_out = -1.0;
         return GF_OK;
     }
@@ -2691,40 +2723,52 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
         return hipSuccess;
     };
     const bool flags_dirty0 = c->flags_dirty;
-    const int nt0 = c->step_threads, sched0 = c->sched_wg;
+    const int nt0 = c->step_threads, sched0 = c->sched_wg, pad0 = c->step_pad;
+    c->tune_trials.clear();
     const bool prof0 = c->prof;
     c->gauges_on = false;
     hipError_t e = copy_all(true);
+    // shapes: workgroup size (cells per thread m^2 / threads) x LDS row
+    // padding x schedule (the resident grid, half of it, one workgroup per
+    // patch)
     static const int cand32[] = {256, 512, 1024}, cand16[] = {64, 128, 256};
     const int *cand = c->m == 16 ? cand16 : cand32;
-    const int scheds[] = {-1, 0};
     for (int ci = 0; ci < 3 && e == hipSuccess && rc == GF_OK; ++ci)
-        for (int si = 0; si < 2 && rc == GF_OK; ++si) {
-            c->step_threads = cand[ci];
-            c->sched_wg = scheds[si];
-            // one untimed step (first use of the shape), then the timed ones
-            c->prof = false;
-            rc = gf_step(c, 1, nullptr, nullptr);
-            if (rc == GF_OK) {
-                c->prof = true;
-                c->prof_launches = 0;
-                c->prof_ms = 0.0;
-                rc = gf_step(c, steps, nullptr, nullptr);
+        for (int pad = 0; pad < 2 && e == hipSuccess && rc == GF_OK; ++pad)
+            for (int si = 0; si < 3 && e == hipSuccess && rc == GF_OK; ++si) {
+                c->step_threads = cand[ci];
+                c->step_pad = pad;
+                int sched = si == 0 ? -1 : 0;
+                if (si == 1) {
+                    const int res = c->prec == GF_FP32 ? gf_step_resident_f32(c->m, cand[ci], pad)
+                                                       : gf_step_resident_f64(c->m, cand[ci], pad);
+                    sched = std::max(1, res / 2);
+                }
+                c->sched_wg = sched;
+                // one untimed step (first use of the shape), then the timed ones
+                c->prof = false;
+                rc = gf_step(c, 1, nullptr, nullptr);
+                if (rc == GF_OK) {
+                    c->prof = true;
+                    c->prof_launches = 0;
+                    c->prof_ms = 0.0;
+                    rc = gf_step(c, steps, nullptr, nullptr);
+                }
+                int64_t n = 0;
+                double ms = 0.0;
+                if (rc == GF_OK) rc = gf_profile_read(c, &n, &ms);
+                if (rc == GF_OK && n > 0) {
+                    const double us = 1e3 * ms / (double)n;
+                    c->tune_trials.push_back({cand[ci], sched, pad, us});
+                    if (best_us < 0.0 || us < best_us) { best_us = us; best_nt = cand[ci]; best_sched = sched; best_pad = pad; }
+                }
+                // restore
+                c->hs = hs0;
+                if ((e = copy_all(false)) != hipSuccess) break;
+                int r2 = push_scen(c);
+                if (rc == GF_OK) rc = r2;
+                c->flags_dirty = flags_dirty0;
             }
-            int64_t n = 0;
-            double ms = 0.0;
-            if (rc == GF_OK) rc = gf_profile_read(c, &n, &ms);
-            if (rc == GF_OK && n > 0) {
-                const double us = 1e3 * ms / (double)n;
-                if (best_us < 0.0 || us < best_us) { best_us = us; best_nt = cand[ci]; best_sched = scheds[si]; }
-            }
-            // restore
-            c->hs = hs0;
-            if ((e = copy_all(false)) != hipSuccess) break;
-            int r2 = push_scen(c);
-            if (rc == GF_OK) rc = r2;
-            c->flags_dirty = flags_dirty0;
-        }
     c->prof = prof0;
     c->prof_launches = 0;
     c->prof_ms = 0.0;
@@ -2735,12 +2779,14 @@ int gf_autotune(gf_ctx *c, int32_t steps, const char *cache_path, int32_t *threa
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(snap);
     if (e != hipSuccess) return fail(c, GF_E_HIP, "autotune snapshot: %s", hipGetErrorString(e));
-    if (rc != GF_OK) { c->step_threads = nt0; c->sched_wg = sched0; return rc; }
+    if (rc != GF_OK) { c->step_threads = nt0; c->sched_wg = sched0; c->step_pad = pad0; return rc; }
     c->step_threads = best_nt;
     c->sched_wg = best_sched;
-    cache_store(cache_path, key.text, best_nt, best_sched, best_us);
+    c->step_pad = best_pad;
+    cache_store(cache_path, key.text, best_nt, best_sched, best_pad, best_us);
     if (threads_out) *threads_out = best_nt;
     if (sched_out) *sched_out = best_sched;
+    if (pad_out) *pad_out = best_pad;
     if (us_per_step_out) *us_per_step_out = best_us;
     return GF_OK;
 }

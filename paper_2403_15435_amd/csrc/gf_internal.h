@@ -136,10 +136,10 @@ struct RefluxArgsBase {
 
 // Launchers, one set per precision (defined in gf_kernels_f32.hip / _f64.hip).
 #define GF_DECL_LAUNCHERS(SFX, R)                                                                  \
-    hipError_t gf_launch_step_##SFX(const gf::StepArgs<R> &a, int m, int nt, int grid, hipStream_t s); \
+    hipError_t gf_launch_step_##SFX(const gf::StepArgs<R> &a, int m, int nt, int pad, int grid, hipStream_t s); \
     int gf_step_threads_ok_##SFX(int m, int nt);                                                   \
     hipError_t gf_launch_dry_##SFX(const gf::StepArgs<R> &a, int m, hipStream_t s);                \
-    int gf_step_resident_##SFX(int m, int nt);                                                     \
+    int gf_step_resident_##SFX(int m, int nt, int pad);                                            \
     hipError_t gf_launch_dryflag_##SFX(const gf::PatchDesc *d, int n, const gf::ScenDev *scen,     \
                                        const R *q0, const R *q1, uint8_t *f0, uint8_t *f1,         \
                                        uint8_t *dstab, int64_t cap, R tau, int m, hipStream_t s);  \

@@ -225,18 +225,69 @@ def test_autotune_leaves_state_unchanged(tmp_path):
             before = ctx.state(0), ctx.time(0), ctx.mass(0)
             cache = str(tmp_path / "tune.txt")
             nt, sched, us = ctx.autotune(steps=3, cache=cache)
-            assert nt in (64, 128, 256) and sched in (-1, 0) and us > 0
+            assert nt in (64, 128, 256) and sched >= -1 and us > 0
+            # 18 timed shapes: workgroup size x LDS row padding x schedule
+            trials = ctx.autotune_trials()
+            print("autotune trials", trials, flush=True)
+            assert len(trials) == 18
+            assert len({t[:3] for t in trials}) == 18
+            assert {t[0] for t in trials} == {64, 128, 256} and {t[2] for t in trials} == {0, 1}
+            assert {t[1] for t in trials if t[1] > 0} and {-1, 0} <= {t[1] for t in trials}
+            best = min(trials, key=lambda t: t[3])
+            assert ctx.autotune_choice() == best and (nt, sched, us) == (best[0], best[1], best[3])
             after = ctx.state(0), ctx.time(0), ctx.mass(0)
             assert np.array_equal(before[0], after[0])
             assert before[1] == after[1]
             assert np.array_equal(before[2], after[2])
             nt2, sched2, us2 = ctx.autotune(steps=3, cache=cache)
             assert (nt2, sched2, us2) == (nt, sched, -1.0)
+            assert ctx.autotune_choice()[2] == best[2]
             assert ctx.step_threads() == nt
         ctx.step(20)
         ctxs.append(ctx)
     assert np.array_equal(ctxs[0].state(0), ctxs[1].state(0))
     assert ctxs[0].time(0) == ctxs[1].time(0)
+
+
+@pytest.mark.parametrize("m,level", [(16, 3), (32, 2)])
+def test_step_shapes_keep_bits(orc, m, level):
+    """Every shape the tuner can choose (workgroup size, LDS row padding,
+    schedule) gives the oracle's bits in FP64 and the same bits as each other
+    in FP32, on a mesh with coarse/fine faces (face records, refluxing)."""
+    sc = inputs.reservoir_fractal(level=level, m=m, L=2000.0, seed=3, radius=500.0)
+    sc.min_level, sc.max_level = 1, 3
+    cand = (64, 128, 256) if m == 16 else (256, 512, 1024)
+    o = orc.Oracle(sc)
+    ctx0 = gf.Context([sc], precision=gf.GF_FP64, max_patches=128)
+    ctx0.set_initial(0, max_passes=2)
+    o.set_leaves(ctx0.leaves(0))
+    init_oracle(o, sc)
+    assert len(set(o.leaves()[:, 1])) >= 2
+    nu, dts = o.advance(30, return_dt=True)
+    ref32 = None
+    for prec in (gf.GF_FP64, gf.GF_FP32):
+        for nt in cand:
+            for pad in (0, 1):
+                for sched in (-1, 3, 0):
+                    print(f"m {m} prec {prec} nt {nt} pad {pad} sched {sched}", flush=True)
+                    ctx = gf.Context([sc], precision=prec, max_patches=128)
+                    ctx.set_step_threads(nt)
+                    ctx.set_step_pad(pad)
+                    ctx.set_schedule(sched)
+                    ctx.set_leaves(0, o.leaves())
+                    ctx.set_initial(0, max_passes=0)
+                    if prec == gf.GF_FP64:
+                        ctx.step(len(dts), dts)
+                        check_fp64(ctx.state(0), o.state(), f"m{m} nt{nt} pad{pad} sched{sched}")
+                    else:
+                        ctx.step(30)
+                        st = ctx.state(0), ctx.time(0), ctx.mass(0)
+                        if ref32 is None:
+                            ref32 = st
+                        assert np.array_equal(st[0], ref32[0]) and st[1] == ref32[1]
+                        assert np.array_equal(st[2], ref32[2])
+    with pytest.raises(gf.GFError):
+        ctx.set_step_pad(2)
 
 
 def test_autotune_on_amr_mesh_keeps_bits(tmp_path):
