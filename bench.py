@@ -465,11 +465,14 @@ def _restore(ctx, snap):
     ctx.set_time(0, t, dt)
 
 
-def valley_headline(steps, warmup, regrid_every=4, t0=4000.0, paths=("fp32_fused", "fp64_fused", "fp64_plain")):
+def valley_headline(steps, warmup, regrid_every=4, t0=4000.0, paths=("fp32_fused", "fp64_fused", "fp64_plain"),
+                    shape=None):
     """The headline: the valley on the fused FP32 path (the timed window),
     then the same window again with the step kernel's launches timed alone,
     and once more with the kernels counting the patches they update; the
-    fused FP64 and plain FP64 paths from the same mesh and state."""
+    fused FP64 and plain FP64 paths from the same mesh and state.  The fused
+    paths take the autotuner's shape, or `shape` = (threads, padding,
+    schedule) for the FP32 path when given (profiling runs)."""
     import paper_2403_15435_amd as gf
     sc, leaves0, state0 = valley_mesh()
     cap = 48000
@@ -485,8 +488,16 @@ def valley_headline(steps, warmup, regrid_every=4, t0=4000.0, paths=("fp32_fused
         else:
             _restore(ctx, snap)
         res = {}
-        if not plain:
+        if shape is not None and name == "fp32_fused":
+            ctx.set_step_threads(shape[0])
+            ctx.set_step_pad(shape[1])
+            ctx.set_schedule(shape[2])
+            res["shape_fixed"] = list(shape)
+        elif not plain:
             res["tuned"] = list(ctx.autotune(steps=3))
+            res["tuned_pad"] = ctx.autotune_choice()[2]
+            res["tune_trials"] = [{"threads": t[0], "schedule": t[1], "pad": t[2], "us_per_step": t[3]}
+                                  for t in ctx.autotune_trials()]
         if snap is None:
             # the warm-up, then the window every path starts from
             amr_window(ctx, warmup, regrid_every)
@@ -504,6 +515,7 @@ def valley_headline(steps, warmup, regrid_every=4, t0=4000.0, paths=("fp32_fused
                     "budget_residual_rel": float(((M[0] - m0[0]) - (M[1] - m0[1]) - (M[2] - m0[2])) / M[0])})
         if name == "fp32_fused":
             res["step_threads"] = ctx.step_threads()
+            res["step_pad"] = shape[1] if shape is not None else res["tuned_pad"]
             # repeat 1: the step kernel's launches timed alone (event pairs)
             _restore(ctx, snap)
             ctx.profile_enable(False, kernel=True)
@@ -757,7 +769,7 @@ def roofline(v32, probe):
     return {"bound": bound, "bound_from": source, "achieved": achieved, "peak": VALU_PEAK_GOPS,
             "unit": "Gop/s (VALU lane operations, non-packed FP32)", "frac": achieved / VALU_PEAK_GOPS,
             "traffic": traffic, "traffic_unit": "HBM bytes per launch (counters x copy calibration)",
-            "kernel": f"step_kernel<32,{v32.get('step_threads')}> fp32", "launches": n,
+            "kernel": f"step_kernel<32,{v32.get('step_threads')},{v32.get('step_pad')}> fp32", "launches": n,
             "avg_launch_us": t * 1e6, "rocprof_avg_launch_us": _num(stats, "step_kernel_avg_us"),
             "cells_updated_per_launch": cells, "algorithmic_ops_per_cell": ALGO_OPS_PER_UPDATE,
             "algorithmic_ops_per_launch": alg_ops,
@@ -786,9 +798,14 @@ def main():
                     help="learned-tagger section: small (a few seeds, bounded), full (50 + 10 seeds)")
     ap.add_argument("--only", choices=["valley", "fp32", "reservoir", "ensemble", "learned", "flood", "lts", "triad"],
                     default=None, help="run only this section and print it (fp32: the headline's FP32 path only)")
+    ap.add_argument("--shape", default=None,
+                    help="threads,padding,schedule of the FP32 step kernel instead of the autotuner's (--only fp32)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM byte counters)")
     args = ap.parse_args()
+    shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
+    if shape is not None and len(shape) != 3:
+        ap.error("--shape takes threads,padding,schedule")
     if args.calibrate_copy:
         calibrate_copy()
         return
@@ -796,7 +813,7 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
     only = {"valley": lambda: valley_headline(args.steps, args.warmup),
-            "fp32": lambda: valley_headline(args.steps, args.warmup, paths=("fp32_fused",)),
+            "fp32": lambda: valley_headline(args.steps, args.warmup, paths=("fp32_fused",), shape=shape),
             "reservoir": lambda: reservoir_section(args.reservoir_steps, 50, args.wet_steps),
             "ensemble": lambda: ensemble(args.ensemble_steps, 10),
             "lts": lambda: lts_compare(args.lts_steps),
