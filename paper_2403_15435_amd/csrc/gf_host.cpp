@@ -6,6 +6,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -150,8 +154,71 @@ struct Scen {
 
 }  // namespace
 
+// Host worker threads kept for the life of a context: a job runs as
+// fn(0..n-1), part 0 on the calling thread, and run() returns when every part
+// has finished.  Starting threads for each descriptor rebuild (one per
+// regrid) cost more than the rebuild itself.
+struct WorkerPool {
+    explicit WorkerPool(int n) : n_(n)
+    {
+        for (int t = 1; t < n_; ++t) th_.emplace_back([this, t] { loop(t); });
+    }
+    ~WorkerPool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    int size() const { return n_; }
+    void run(const std::function<void(int)> &fn)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &fn;
+            pending_ = n_ - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        fn(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [this] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    void loop(int t)
+    {
+        unsigned seen = 0;
+        for (;;) {
+            const std::function<void(int)> *job;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                job = job_;
+            }
+            (*job)(t);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)> *job_ = nullptr;
+    unsigned gen_ = 0;
+    int pending_ = 0;
+    bool stop_ = false;
+};
+
 struct gf_ctx {
     gf_config cfg{};
+    std::unique_ptr<WorkerPool> pool;   // descriptor rebuilds, started on first use
     int prec = GF_FP64;
     int m = 32;
     int step_threads = 256;   // workgroup size of the step kernel
@@ -643,6 +710,7 @@ int rebuild_work(gf_ctx *c)
     std::vector<char> has((size_t)total, 0);
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int nth = (int)std::min<int64_t>(std::min<unsigned>(hw, 16u), std::max<int64_t>(1, total / 2048));
+    if (nth > 1 && (!c->pool || c->pool->size() < nth)) c->pool.reset(new WorkerPool(nth));
     std::vector<std::string> errs((size_t)nth);
     std::vector<int64_t> err_at((size_t)nth, -1);
     auto work = [&](int t) {
@@ -683,9 +751,9 @@ int rebuild_work(gf_ctx *c)
     if (nth == 1) {
         work(0);
     } else {
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nth; ++t) pool.emplace_back(work, t);
-        for (auto &th : pool) th.join();
+        // the pool may be wider than this rebuild needs: extra parts idle
+        const std::function<void(int)> job = [&](int t) { if (t < nth) work(t); };
+        c->pool->run(job);
     }
     for (int t = 0; t < nth; ++t)
         if (err_at[(size_t)t] >= 0) {
