@@ -752,8 +752,14 @@ def roofline(v32, probe):
     dense = v32["cell_updates"] / max(v32["accepted_steps"] + v32["rejected"], 1)
     alg_ops = ALGO_OPS_PER_UPDATE * cells
     hbm_gbs = BYTES_PER_UPDATE["f32"] * cells / t / 1e9
-    kv = read_summary(VALLEY_COUNTERS)
-    stats = read_summary(VALLEY_STATS)
+    # the committed summaries count only when taken on the same kernel
+    # sources and the same step-kernel shape (threads, LDS row padding)
+    shape = f"{v32.get('step_threads')},{v32.get('step_pad')}"
+    kv, stats = read_summary(VALLEY_COUNTERS), read_summary(VALLEY_STATS)
+    if kv and kv.get("kernel_shape") != shape:
+        kv = None
+    if stats and stats.get("kernel_shape") != shape:
+        stats = None
     valu_per_launch = _num(kv, "valu_lane_ops_per_launch")
     traffic = None
     if kv and _num(kv, "fetch_kib_per_launch") is not None:
@@ -764,7 +770,8 @@ def roofline(v32, probe):
     if issued_frac is not None and traffic_frac is not None:
         bound, source = ("alu", "counters") if issued_frac >= traffic_frac else ("hbm", "counters")
     else:
-        bound, source = "alu", "no counters for these kernel sources: the method's arithmetic intensity"
+        bound, source = "alu", ("no counters for these kernel sources and this shape: "
+                                "the method's arithmetic intensity")
     achieved = alg_ops / t / 1e9
     return {"bound": bound, "bound_from": source, "achieved": achieved, "peak": VALU_PEAK_GOPS,
             "unit": "Gop/s (VALU lane operations, non-packed FP32)", "frac": achieved / VALU_PEAK_GOPS,

@@ -281,8 +281,11 @@ int gf_get_step_threads(gf_ctx *ctx, int32_t *nt);
  * Errors: GF_E_UNSUPPORTED for other values. */
 int gf_set_step_pad(gf_ctx *ctx, int32_t pad);
 /* Autotuner: time every built step-kernel shape for `steps` steps on the
- * context's current state, keep the fastest, and restore the state, clocks
- * and budgets after each trial, so the simulation is unchanged.  Shapes:
+ * context's current state and restore the state, clocks and budgets after
+ * each trial, so the simulation is unchanged.  It keeps the first shape in
+ * the order below (fewer threads, no padding, resident grid first) whose
+ * time is within 2% of the fastest, so that a near tie resolves the same
+ * way from run to run.  Shapes:
  * workgroup size (m = 32: 256, 512, 1024 threads, i.e. 4, 2, 1 cells per
  * thread; m = 16: 64, 128, 256) x LDS row padding (0, 1) x schedule (the
  * resident persistent grid, half of it, one workgroup per patch): 18.

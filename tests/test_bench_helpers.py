@@ -36,11 +36,13 @@ def test_roofline_object(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "source_digest", lambda: "c" * 64)
     # 400 launches of 800 us, 20000 patches of 1024 cells updated per launch
     v32 = {"step_kernel_launches": 400, "step_kernel_avg_us": 800.0, "patches_full_update": 400 * 20000,
-           "cell_updates": 400 * 25000 * 1024, "accepted_steps": 400, "rejected": 0, "step_threads": 512}
+           "cell_updates": 400 * 25000 * 1024, "accepted_steps": 400, "rejected": 0, "step_threads": 512,
+           "step_pad": 0}
     probe = {"best_GBps": 6000.0}
     monkeypatch.setattr(bench, "VALLEY_COUNTERS", _summary(tmp_path, "c" * 64, valu_lane_ops_per_launch=2.0e10,
                                                            fetch_kib_per_launch=500000.0, fetch_scale=2.0,
-                                                           write_kib_per_launch=250000.0, write_scale=1.0))
+                                                           write_kib_per_launch=250000.0, write_scale=1.0,
+                                                           kernel_shape="512,0"))
     monkeypatch.setattr(bench, "VALLEY_STATS", str(tmp_path / "none.txt"))
     r = bench.roofline(v32, probe)
     cells = 20000 * 1024.0
@@ -54,6 +56,9 @@ def test_roofline_object(tmp_path, monkeypatch):
     # issued VALU 2e10 / 800 us = 25 Tops/s of 39.3: above the traffic's 1.28 TB/s of 8
     assert r["bound"] == "alu" and r["bound_from"] == "counters"
     assert r["issued_valu_ops_per_cell"] == pytest.approx(2.0e10 / cells)
+    # counters of another shape (LDS row padding 1) do not count
+    r3 = bench.roofline(dict(v32, step_pad=1), probe)
+    assert r3["traffic"] is None and r3["issued_valu_frac"] is None
     monkeypatch.setattr(bench, "VALLEY_COUNTERS", str(tmp_path / "none.txt"))
     r2 = bench.roofline(v32, None)
     assert r2["traffic"] is None and r2["issued_valu_frac"] is None and r2["bound"] == "alu"

@@ -233,7 +233,9 @@ def test_autotune_leaves_state_unchanged(tmp_path):
             assert len({t[:3] for t in trials}) == 18
             assert {t[0] for t in trials} == {64, 128, 256} and {t[2] for t in trials} == {0, 1}
             assert {t[1] for t in trials if t[1] > 0} and {-1, 0} <= {t[1] for t in trials}
-            best = min(trials, key=lambda t: t[3])
+            # the first trial within 2% of the fastest
+            fastest = min(t[3] for t in trials)
+            best = next(t for t in trials if t[3] <= 1.02 * fastest)
             assert ctx.autotune_choice() == best and (nt, sched, us) == (best[0], best[1], best[3])
             after = ctx.state(0), ctx.time(0), ctx.mass(0)
             assert np.array_equal(before[0], after[0])
