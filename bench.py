@@ -1,8 +1,8 @@
 """Benchmark: cell updates per second of the FP32 batched adaptive patch
 update on one MI355X, against the plain FP64 path on the same inputs.
 
-Headline workload (configuration 3, the adaptive one the metric names): the
-AMR inflow valley, 20 km x 10 km, side slope 0.05 with 2 m rms fractal
+Headline workload (the adaptive one the metric names): the AMR inflow
+valley, 20 km x 10 km, side slope 0.05 with 2 m rms fractal
 roughness, 16 x 8 trees, levels 0-6 of 32 x 32 patches (finest cells 0.61 m,
 about 25 000 leaves), inflow 5000 m^3/s over 200 m on the hydrograph's
 plateau, Manning n = 0.04, extrapolation outflow, walls; the mesh built from
@@ -41,7 +41,7 @@ BYTES_PER_UPDATE = {"f32": 28.0, "f64": 56.0}
 ALGO_OPS_PER_UPDATE = 500.0
 # non-packed FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes per cycle x 2.4 GHz
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-VALLEY_DESC = ("AMR inflow valley (configuration 3): 20 km x 10 km V valley, side slope 0.05, 2 m rms fractal "
+VALLEY_DESC = ("AMR inflow valley: 20 km x 10 km V valley, side slope 0.05, 2 m rms fractal "
                "roughness, 16x8 trees, levels 0-6 of 32x32 patches (finest cells 0.61 m), inflow 5000 m^3/s over "
                "200 m (hydrograph plateau, from t = 4000 s), n = 0.04, extrapolation outflow, walls; mesh built "
                "from level 0 by plain-tagger passes; tag and regrid every 4 steps inside the timed window")
@@ -306,7 +306,7 @@ def learned_tagger(n_train=50, n_eval=10, steps=2000, window=16, check=4, iters=
     its centre drawn from U[2.5 km, 7.5 km]^2 by the seed.  Trained on the GPU
     from plain-tagger windows (a sample every 16 steps: every refine label,
     twice as many others drawn at random) of seeds 5001.., evaluated on the
-    unseen seeds 5051..: the plain tagger every 4 steps (the judge), every 16
+    unseen seeds 5051..: the plain tagger every 4 steps (the reference), every 16
     steps, and the network every 16 steps with the plain-tagger fallback at
     the 4-step checks."""
     import paper_2403_15435_amd as gf

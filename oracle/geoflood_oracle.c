@@ -109,7 +109,7 @@ typedef struct {
     long steps, rejected;
     double clamp_mass, bnd_mass;
     double m0;
-    int bathy_f32;       /* hold bathymetry rounded to float (to judge an FP32 run) */
+    int bathy_f32;       /* hold bathymetry rounded to float (to check an FP32 run) */
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -384,7 +384,7 @@ static void leaf_bathymetry(orc_sim *s, leaf_t *L)
 }
 
 /* Round every bathymetry value to the nearest float (and keep doing so after
- * regrids): the FP32 library path is judged against FP64 arithmetic on the
+ * regrids): the FP32 library path is checked against FP64 arithmetic on the
  * same rounded bed. */
 void orc_set_bathy_f32(orc_sim *s, int on)
 {

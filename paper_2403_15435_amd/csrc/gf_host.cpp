@@ -2427,7 +2427,7 @@ int gf_run(gf_ctx *c, int32_t nsteps, int32_t mode, int32_t check_every, int32_t
                 learned.resize((size_t)n);
                 rc = gf_net_predict(c, learned.data(), n, &nn);
                 if (rc) break;
-                // the plain tagger stays the judge: its refine requests always
+                // the plain tagger stays the reference: its refine requests always
                 // hold, and a coarsening needs its agreement
                 for (int64_t i = 0; i < n; ++i) {
                     int8_t f = learned[(size_t)i];

@@ -50,7 +50,7 @@ def test_reservoir_2048_against_oracle(orc, prec):
     if not f32:
         assert np.array_equal(g[:, :3], r[:, :3])
         return
-    # FP32, judged with the front zone of the bar: a cell is at a front when
+    # FP32, checked with the front zone of the bar: a cell is at a front when
     # a cell of depth <= 1e-2 m (either solution) lies within 2 cells
     prof, rel_away, front = _fp32_profile(sc, o.leaves(), g, r)
     print("  fp32 max rel by distance to the front (cells 1..8): " + " ".join(f"{x:.1e}" for x in prof), flush=True)
@@ -85,7 +85,7 @@ def _fp32_profile(sc, lv, g, r, level=6):
 def test_reservoir_2048_fp32_horizons(orc):
     """The FP32 path on the 2048^2 reservoir against the FP64 oracle (OpenMP)
     at 1, 10, 100 and 2000 steps of the oracle's lengths, both from the FP32
-    initial state on the rounded bed, judged with the 2-cell front zone.
+    initial state on the rounded bed, checked with the 2-cell front zone.
     Reported at every horizon (max relative error by distance to the front,
     beyond the zone, absolute within it, flooded area); asserted: the volume
     budget, the bar at 1 step; a horizon where the bar is not met is reported

@@ -216,12 +216,12 @@ def _dilated_run(ctx, sc, nsteps, check=4, regrid_every=16):
 def test_learned_tagger_gain():
     """Trained on the GPU from plain-tagger windows of four seeded runs, the
     network anticipates refinement on an unseen run.  Against the plain
-    tagger every 4 steps (the judge), every 16 steps, and every 16 steps with
+    tagger every 4 steps (the reference), every 16 steps, and every 16 steps with
     its refine requests dilated by one leaf (a trivial anticipating tagger),
     regridding every 16 steps with the network: misses fewer refine requests
     at the 4-step checks than either 16-step tagger, at no more work
-    (leaf-steps) than the dilated one and within 1.25 times the judge's; needs
-    fewer regrids than the judge; ends closer to the judge's depths than the
+    (leaf-steps) than the dilated one and within 1.25 times the reference's; needs
+    fewer regrids than the reference; ends closer to the reference's depths than the
     plain tagger every 16 steps."""
     from helpers import to_finest
     X, Y = [], []
