@@ -3,4 +3,7 @@
 #define REAL float
 #define SFX f32
 #define KNS k32
+#ifndef GF_RIEMANN_FP64
+#define GF_RIEMANN_FP64 1
+#endif
 #include "gf_kernels.inc"

@@ -2,4 +2,5 @@
 #define REAL double
 #define SFX f64
 #define KNS k64
+#define GF_RIEMANN_FP64 0
 #include "gf_kernels.inc"

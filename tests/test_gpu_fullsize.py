@@ -56,12 +56,9 @@ def test_reservoir_2048_against_oracle(orc, prec):
     print("  fp32 max rel by distance to the front (cells 1..8): " + " ".join(f"{x:.1e}" for x in prof), flush=True)
     print(f"  fp32 after 10 steps: rel beyond 2 cells {rel_away:.3e} (bar 2e-5), abs within {front:.3e} m (bar 1e-3)",
           flush=True)
-    if rel_away > 2e-5 or front > 1e-3:
-        pytest.xfail(f"FP32 bars not met at 10 steps: {rel_away:.2e} beyond the 2-cell front zone (2e-5), "
-                     f"{front:.2e} m within it (1e-3); by distance "
-                     + " ".join(f"{x:.1e}" for x in prof) + ".  Thin cells just wetted by the dam break get their "
-                     "depth as a sum of O(1 m) FP32 fluctuations (1e-7 m resolution, 1e-5 of a 1 cm depth); the FP64 "
-                     "oracle with only its stored state rounded to FP32 stays at 2e-7 there")
+    # the bar; it holds because the FP32 path solves its Riemann problems in
+    # FP64 (waves rounded in FP32 put 1e-4 errors into the thin cells here)
+    assert rel_away <= 2e-5 and front <= 1e-3
 
 
 def _fp32_profile(sc, lv, g, r, level=6):
@@ -88,8 +85,8 @@ def test_reservoir_2048_fp32_horizons(orc):
     initial state on the rounded bed, checked with the 2-cell front zone.
     Reported at every horizon (max relative error by distance to the front,
     beyond the zone, absolute within it, flooded area); asserted: the volume
-    budget, the bar at 1 step; a horizon where the bar is not met is reported
-    as an expected failure with its numbers."""
+    budget, the bar at 1 and 10 steps; a later horizon where the bar is not met
+    is reported as an expected failure with its numbers."""
     sc = inputs.reservoir_fractal(level=6, m=32, L=10000.0, seed=2, radius=400.0, h_res=20.0, manning_n=0.033)
     o = orc.Oracle(sc, cfl_desired=0.9)
     o.set_bathy_f32(True)
@@ -110,15 +107,17 @@ def test_reservoir_2048_fp32_horizons(orc):
         fl_g, fl_o = int(np.count_nonzero(g[:, 0] > 0.1)), int(np.count_nonzero(r[:, 0] > 0.1))
         print(f"  {horizon} steps (t = {o.t:.1f} s): rel beyond 2 cells {rel_away:.2e}, abs within {front:.2e} m, "
               f"flooded cells {fl_g} vs {fl_o}; by distance " + " ".join(f"{x:.1e}" for x in prof), flush=True)
-        if horizon == 1:
+        if horizon <= 10:
             assert rel_away <= 2e-5 and front <= 1e-3
         if rel_away > 2e-5 or front > 1e-3:
             misses.append(f"{horizon} steps: {rel_away:.1e} beyond the zone, {front:.1e} m within")
     M, cl, bd = ctx.mass(0)
     assert abs(M - m0 - cl - bd) <= 1e-6 * m0
     if misses:
-        pytest.xfail("FP32 bar not met at " + "; ".join(misses) + " (cancellation in the update of thin cells "
-                     "just wetted by the dam break; see the 10-step test)")
+        pytest.xfail("FP32 bar not met at " + "; ".join(misses) + ".  The FP32 state's own rounding sets this "
+                     "limit: the FP64 oracle with only its stored state rounded to FP32 every step already reaches "
+                     "1.5e-5 beyond the zone at 100 steps, and the wet/dry fronts on the rough bed amplify any "
+                     "such difference over longer horizons (the flooded areas stay equal to a few cells)")
 
 
 def test_ensemble_256_sampled_scenarios_against_oracle(orc):
