@@ -99,7 +99,19 @@ typedef struct {
     void *hip_stream;            /* hipStream_t or NULL */
     const char *autotune_cache;  /* nullable: cache file gf_autotune uses when its own path is NULL;
                                   * copied at gf_create */
+    int32_t limiter;             /* limiter of the f-wave corrections (Section 3.2, eq.
+                                  * (wpa_update_corrections), limiters that keep the scheme
+                                  * TVD): GF_LIMITER_MC (0, the default), _MINMOD, _SUPERBEE,
+                                  * _VANLEER, or _NONE (first order: no corrections) */
+    int32_t transverse;          /* the 2D extension of Section 3.2: GF_TRANSVERSE_CORRECTED
+                                  * (0, the default: each cell's net normal increment,
+                                  * corrections included, split into the other direction's
+                                  * fluxes) or GF_TRANSVERSE_NONE (no transverse terms; stable
+                                  * only to a Courant number of about 0.5) */
 } gf_config;
+
+enum { GF_LIMITER_MC = 0, GF_LIMITER_MINMOD = 1, GF_LIMITER_SUPERBEE = 2, GF_LIMITER_VANLEER = 3, GF_LIMITER_NONE = 4 };
+enum { GF_TRANSVERSE_CORRECTED = 0, GF_TRANSVERSE_NONE = 1 };
 
 typedef struct {
     int64_t steps;               /* accepted steps over all scenarios in this call */

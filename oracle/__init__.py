@@ -76,6 +76,9 @@ def lib(variant=None):
         L.orc_advance.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
         L.orc_advance_lts.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
         L.orc_set_bathy_f32.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_scheme.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.orc_wave_limiter.argtypes = [C.c_int, C.c_double]
+        L.orc_wave_limiter.restype = C.c_double
         L.orc_mass.argtypes = [C.c_void_p, _dp]
         L.orc_tag.argtypes = [C.c_void_p, C.POINTER(C.c_byte)]
         L.orc_set_tag_rules.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, _dp]
@@ -118,6 +121,11 @@ def threads() -> int:
     return lib().orc_get_threads()
 
 
+def wave_limiter(lim: int, theta: float) -> float:
+    """phi(theta) of limiter `lim` (0 MC, 1 minmod, 2 superbee, 3 van Leer, 4 none)."""
+    return lib().orc_wave_limiter(lim, theta)
+
+
 def cbrt(x: float) -> float:
     """The oracle's cube root (used by the friction term)."""
     return lib().orc_cbrt(float(x))
@@ -150,7 +158,7 @@ class Oracle:
 
     def __init__(self, sc, g: float = G_DEFAULT, tau: float = TAU_DEFAULT,
                  cfl_desired: float = 0.9, cfl_max: float = 1.0, leaves: Optional[np.ndarray] = None,
-                 variant=None):
+                 variant=None, limiter: int = 0, transverse: int = 0):
         self.sc = sc
         self.m = sc.m
         self._L = lib(variant)
@@ -161,6 +169,8 @@ class Oracle:
         nh = len(sc.hydro) if sc.hydro else 0
         L = self._L
         self._p = L.orc_create(_d(dp), ip.ctypes.data_as(_ip), _d(hy), nh)
+        # limiter: 0 MC, 1 minmod, 2 superbee, 3 van Leer, 4 none; transverse: 0 corrected, 1 none
+        L.orc_set_scheme(self._p, limiter, transverse)
         rg = np.asarray(sc.regions if sc.regions else [(0.0,) * 6], dtype=np.float64).reshape(-1)
         gr = np.asarray(sc.grades if sc.grades else [(0.0,) * 3], dtype=np.float64).reshape(-1)
         L.orc_set_tag_rules(self._p, sc.tag_u_refine, sc.tag_q_refine, len(sc.regions) if sc.regions else 0, _d(rg),

@@ -110,6 +110,9 @@ typedef struct {
     double clamp_mass, bnd_mass;
     double m0;
     int bathy_f32;       /* hold bathymetry rounded to float (to check an FP32 run) */
+    /* scheme options: limiter 0 MC, 1 minmod, 2 superbee, 3 van Leer, 4 none;
+       transverse 0 corrected (the default), 1 none */
+    int limiter, transverse;
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -959,6 +962,36 @@ static double mc_limiter(double th)
     return r > 0.0 ? r : 0.0;
 }
 
+/* The TVD limiters the paper's Section 3.2 allows, as functions of the ratio
+ * theta of the upwind wave's projection to the wave itself (LeVeque 2002,
+ * Section 6.12): MC, minmod phi = max(0, min(1, theta)), superbee
+ * phi = max(0, min(1, 2 theta), min(2, theta)), van Leer
+ * phi = (theta + |theta|) / (1 + |theta|), that is 2 - 2 / (1 + theta) for
+ * theta > 0 and 0 otherwise; "none" gives the first-order method. */
+static double wave_limiter(int lim, double th)
+{
+    double r, a, b;
+    switch (lim) {
+    case 0: return mc_limiter(th);
+    case 1: r = th < 1.0 ? th : 1.0; return r > 0.0 ? r : 0.0;
+    case 2:
+        a = th * 2.0 < 1.0 ? th * 2.0 : 1.0;
+        b = th < 2.0 ? th : 2.0;
+        r = a > b ? a : b;
+        return r > 0.0 ? r : 0.0;
+    case 3: return th > 0.0 ? 2.0 - 2.0 / (1.0 + th) : 0.0;   /* (th + |th|) / (1 + |th|) */
+    default: return 0.0;
+    }
+}
+
+void orc_set_scheme(orc_sim *s, int limiter, int transverse)
+{
+    s->limiter = limiter;
+    s->transverse = transverse;
+}
+
+double orc_wave_limiter(int lim, double th) { return wave_limiter(lim, th); }
+
 /* Transverse split of increment d = (h, p, q) where p is the momentum normal
  * to the sweep and q the transverse momentum.  Target cell state (hk, pk, qk,
  * bk), transverse neighbour (hn, pn, qn, bn).  want_pos selects B+ (the part
@@ -1043,7 +1076,7 @@ static void correction_flux(const orc_sim *s, const edge_t *E, int e, int r, dou
         if (zz == 0.0) continue;
         up = (ed->s[p] > 0.0) ? &E[(r + 1) * ne + e] : &E[(r + 1) * ne + (e + 2)];
         ZI = &up->z[3 * p];
-        phi = mc_limiter((ZI[0] * Z[0] + ZI[1] * Z[1] + ZI[2] * Z[2]) / zz);
+        phi = wave_limiter(s->limiter, (ZI[0] * Z[0] + ZI[1] * Z[1] + ZI[2] * Z[2]) / zz);
         c = sg * (1.0 - dtdx * fabs(ed->s[p]));
         for (k = 0; k < 3; ++k) acc[k] += c * (phi * Z[k]);
     }
@@ -1134,8 +1167,9 @@ static double update_all(orc_sim *s, double dt, const char *act)
                 for (e = 0; e < m; ++e)
                     for (f = 0; f < 3; ++f)
                         Dn[((r + 1) * m + e) * 3 + f] = DP[((r + 1) * (m + 1) + e) * 3 + f] + DM[((r + 1) * (m + 1) + e + 1) * 3 + f];
-            /* transverse edge between rows r and r+1 at position k */
-            for (r = -1; r < m; ++r)
+            /* transverse edge between rows r and r+1 at position k (none:
+               the transverse fluxes stay zero) */
+            for (r = -1; r < m && s->transverse == 0; ++r)
                 for (e = 0; e < m; ++e) {
                     int ga, gb;
                     double up[3], dn[3], o[3];

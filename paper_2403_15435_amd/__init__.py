@@ -36,7 +36,7 @@ class gf_config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("m", C.c_int32), ("g", C.c_double), ("dry_tol", C.c_double),
                 ("cfl_desired", C.c_double), ("cfl_max", C.c_double), ("n_scen", C.c_int32),
                 ("scen", C.POINTER(gf_scenario_desc)), ("max_patches", C.c_int64), ("hip_stream", C.c_void_p),
-                ("autotune_cache", C.c_char_p)]
+                ("autotune_cache", C.c_char_p), ("limiter", C.c_int32), ("transverse", C.c_int32)]
 
 
 class gf_step_stats(C.Structure):
@@ -52,6 +52,8 @@ class gf_run_stats(C.Structure):
 
 GF_RUN_PLAIN, GF_RUN_SPARSE, GF_RUN_LEARNED = 0, 1, 2
 GF_TAG_PLAIN, GF_TAG_LEARNED = 0, 1
+GF_LIMITER_MC, GF_LIMITER_MINMOD, GF_LIMITER_SUPERBEE, GF_LIMITER_VANLEER, GF_LIMITER_NONE = 0, 1, 2, 3, 4
+GF_TRANSVERSE_CORRECTED, GF_TRANSVERSE_NONE = 0, 1
 
 # void ic(user, scen, level, x0, y0, dx, dy, nx, ny, const double *b, double *h, double *hu, double *hv)
 GF_IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -177,7 +179,8 @@ class Context:
 
     def __init__(self, scenarios: Sequence, precision: int = GF_FP64, max_patches: Optional[int] = None,
                  g: float = 9.81, dry_tol: float = 1e-4, cfl_desired: float = 0.9, cfl_max: float = 1.0,
-                 stream=None, autotune_cache: Optional[str] = None):
+                 stream=None, autotune_cache: Optional[str] = None, limiter: int = GF_LIMITER_MC,
+                 transverse: int = GF_TRANSVERSE_CORRECTED):
         L = load()
         self.L = L
         self.scenarios = list(scenarios)
@@ -213,7 +216,8 @@ class Context:
         cfg = gf_config(precision=precision, m=self.m, g=g, dry_tol=dry_tol, cfl_desired=cfl_desired,
                         cfl_max=cfl_max, n_scen=len(self.scenarios), scen=descs, max_patches=max_patches,
                         hip_stream=stream if stream is not None else _stream_handle(),
-                        autotune_cache=autotune_cache.encode() if autotune_cache else None)
+                        autotune_cache=autotune_cache.encode() if autotune_cache else None,
+                        limiter=limiter, transverse=transverse)
         self._p = C.c_void_p()
         rc = L.gf_create(C.byref(cfg), C.byref(self._p))
         if rc != 0:

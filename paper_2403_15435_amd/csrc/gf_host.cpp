@@ -859,6 +859,7 @@ void fill_step_args(gf_ctx *c, StepArgs<T> &a, double dt_fixed, int mode, T tau)
     a.clamp_acc0 = c->cacc[0]; a.clamp_acc1 = c->cacc[1]; a.bnd_acc0 = c->bacc[0]; a.bnd_acc1 = c->bacc[1];
     a.reg = (T *)c->reg; a.cap = c->cap; a.dt_fixed = dt_fixed; a.mode = mode;
     a.g = c->cfg.g; a.cfl_desired = c->cfg.cfl_desired; a.cfl_max = c->cfg.cfl_max;
+    a.limiter = c->cfg.limiter; a.transverse = c->cfg.transverse;
     a.tau = tau; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter;
     a.queue = c->d_queue; a.persistent = 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
     a.wet_list = c->d_wet; a.wet_count = c->d_wet_count;
@@ -1296,6 +1297,8 @@ int gf_create(const gf_config *cfg, gf_ctx **out)
     if (cfg->precision != GF_FP32 && cfg->precision != GF_FP64) return GF_E_INVALID;
     if (cfg->n_scen <= 0 || !cfg->scen || cfg->max_patches <= 0) return GF_E_INVALID;
     if (!(cfg->g > 0) || !(cfg->dry_tol > 0) || !(cfg->cfl_desired > 0) || !(cfg->cfl_max >= cfg->cfl_desired)) return GF_E_INVALID;
+    if (cfg->limiter < GF_LIMITER_MC || cfg->limiter > GF_LIMITER_NONE) return GF_E_INVALID;
+    if (cfg->transverse != GF_TRANSVERSE_CORRECTED && cfg->transverse != GF_TRANSVERSE_NONE) return GF_E_INVALID;
     gf_ctx *c = new gf_ctx();
     c->cfg = *cfg;
     c->cfg.scen = nullptr;

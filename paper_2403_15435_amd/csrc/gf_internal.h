@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/geoflood.h"   // the GF_LIMITER_* and GF_TRANSVERSE_* values
+
 namespace gf {
 
 // Halo regions of a patch (2-cell ghost layer), each fed by one source:
@@ -120,6 +122,8 @@ struct StepArgs {
     unsigned long long *stats;   // [0] patches through step_kernel, [1] stable dry patches (or null)
     int32_t lts;                 // local time stepping: the levels starting a substep at `tick` only
     int32_t tick;
+    int32_t limiter;             // GF_LIMITER_*: the wave limiter of the corrections
+    int32_t transverse;          // GF_TRANSVERSE_*: corrected transverse terms or none
 };
 
 struct RefluxArgsBase {

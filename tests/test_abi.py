@@ -76,7 +76,8 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 
 @pytest.mark.parametrize("bad", ["u", "q", "n_regions", "region_box", "region_levels", "region_fraction",
-                                 "n_grades", "grade_quantity", "grade_threshold", "grade_level", "null_regions"])
+                                 "n_grades", "grade_quantity", "grade_threshold", "grade_level", "null_regions",
+                                 "limiter", "transverse"])
 def test_create_rejects_invalid_refinement_rules(bad):
     """Rules are checked before anything touches the device."""
     import paper_2403_15435_amd as gf
@@ -110,6 +111,10 @@ def test_create_rejects_invalid_refinement_rules(bad):
         d.regions = None
     cfg = gf.gf_config(precision=gf.GF_FP64, m=16, g=9.81, dry_tol=1e-4, cfl_desired=0.9, cfl_max=1.0, n_scen=1,
                        scen=ctypes.pointer(d), max_patches=16, hip_stream=None)
+    if bad == "limiter":
+        cfg.limiter = 5
+    elif bad == "transverse":
+        cfg.transverse = 2
     out = ctypes.c_void_p()
     assert L.gf_create(ctypes.byref(cfg), ctypes.byref(out)) == gf.GF_E_INVALID
     assert not out.value

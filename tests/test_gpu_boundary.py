@@ -148,3 +148,44 @@ def test_train_step_on_device_batch_equals_host_batch():
     assert np.array_equal(a.net_params(), b.net_params())
     with pytest.raises(ValueError):
         b.net_train_step_dev(xt[:, :100], yt, cw, lr=1e-3)
+
+
+@pytest.mark.parametrize("limiter,transverse", [(gf.GF_LIMITER_MINMOD, 0), (gf.GF_LIMITER_SUPERBEE, 0),
+                                                (gf.GF_LIMITER_VANLEER, 0), (gf.GF_LIMITER_NONE, 0),
+                                                (gf.GF_LIMITER_MC, gf.GF_TRANSVERSE_NONE)])
+def test_scheme_options_match_oracle(orc, limiter, transverse):
+    """gf_config.limiter and .transverse against the oracle with the same
+    options: FP64 bit for bit over 30 adaptive steps of the fractal reservoir
+    (wet/dry fronts, friction, walls) on the fused and the plain path, FP32
+    within its bar after 10 steps; the options change the result."""
+    sc = inputs.reservoir_fractal(level=3, m=16, L=2000.0, seed=2, radius=300.0)
+    cfl = 0.45 if transverse == gf.GF_TRANSVERSE_NONE else 0.9
+    o = orc.Oracle(sc, cfl_desired=cfl, limiter=limiter, transverse=transverse)
+    init_oracle(o, sc)
+    st0 = o.state()
+    nu, dts = o.advance(30, return_dt=True)
+    print(f"limiter {limiter} transverse {transverse}: oracle to t = {o.t:.3f} s", flush=True)
+    for plain in (False, True):
+        ctx = gf.Context([sc], precision=gf.GF_FP64, max_patches=64, cfl_desired=cfl, limiter=limiter,
+                         transverse=transverse)
+        ctx.set_state(0, st0)
+        ctx.step(30, plain=plain)
+        assert ctx.time(0)[:2] == (o.t, o.dt)
+        assert np.array_equal(ctx.state(0)[:, :3], o.state()[:, :3])
+    default = gf.Context([sc], precision=gf.GF_FP64, max_patches=64, cfl_desired=cfl)
+    default.set_state(0, st0)
+    default.step(30)
+    assert not np.array_equal(default.state(0)[:, :3], o.state()[:, :3])
+    # FP32 against the oracle on the rounded bed and state
+    o32 = orc.Oracle(sc, cfl_desired=cfl, limiter=limiter, transverse=transverse)
+    o32.set_bathy_f32(True)
+    init_oracle(o32, sc, "f32")
+    c32 = gf.Context([sc], precision=gf.GF_FP32, max_patches=64, cfl_desired=cfl, limiter=limiter,
+                     transverse=transverse)
+    c32.set_state(0, o32.state().astype(np.float32).astype(np.float64)[:, :3])
+    _, d32 = o32.advance(10, return_dt=True)
+    c32.step(len(d32), d32)
+    from helpers import check_fp32
+    rel, front = check_fp32(sc, o32.leaves(), c32.state(0), o32.state(), 3)
+    print(f"  fp32: {rel:.2e} beyond fronts, {front:.2e} m at fronts", flush=True)
+    assert rel <= 2e-5 and front <= 1e-3
