@@ -152,6 +152,14 @@ struct Scen {
     double clamp_base = 0.0, bnd_base = 0.0;
 };
 
+// a leaf of the list a regrid builds: refined (kind 0, quadrant q of leaf
+// src), coarsened into its parent (1, first child src), or kept (2, src)
+struct RgPending {
+    int kind;
+    int64_t src;
+    int q;
+};
+
 }  // namespace
 
 // Host worker threads kept for the life of a context: a job runs as
@@ -295,8 +303,19 @@ struct gf_ctx {
     std::vector<int32_t> old_at, old_task_at;
     std::vector<char> freed_mark;
     std::vector<ScenDev> hs;
-    std::vector<int8_t> last_flags;
+    std::vector<int8_t, PinnedAlloc<int8_t>> last_flags;
     bool topo_dirty = true;
+    // working memory of gf_regrid, the descriptor rebuild and the budget
+    // fold, kept between calls: a regrid of a large mesh changes a few leaves,
+    // and buffers of the whole leaf list allocated afresh each time cost more
+    // in page faults than the work done in them
+    std::vector<Leaf> rg_leaves;
+    std::vector<RgPending> rg_pend;
+    std::vector<char> rg_ref, rg_coa;
+    LeafMap rg_internal;
+    std::vector<RefluxTask> rb_task;
+    std::vector<char> rb_has;
+    std::vector<double, PinnedAlloc<double>> fold_buf;
     // profiling: prof times the steps with an event pair per stretch of
     // launches (ev[0] before its first step, ev[1] before the next
     // synchronisation); prof_stats has the kernels count patches
@@ -536,7 +555,9 @@ void sort_leaves(const gf_ctx *c, Scen &s)
 {
     const int mi = s.d.mi;
     const size_t n = s.leaves.size();
-    std::vector<std::pair<int64_t, uint64_t>> key(n);
+    // kept between calls (a regrid sorts the whole list each time)
+    static thread_local std::vector<std::pair<int64_t, uint64_t>> key;
+    key.resize(n);
     for (size_t k = 0; k < n; ++k) {
         const Leaf &a = s.leaves[k];
         key[k].first = (a.PJ >> a.level) * mi + (a.PI >> a.level);
@@ -706,8 +727,11 @@ int rebuild_work(gf_ctx *c)
         total += (int64_t)c->sc[(size_t)si].leaves.size();
     }
     c->desc.resize((size_t)total);
-    std::vector<RefluxTask> task((size_t)total);
-    std::vector<char> has((size_t)total, 0);
+    // a task entry is read only where has is set, which writes it first
+    std::vector<RefluxTask> &task = c->rb_task;
+    std::vector<char> &has = c->rb_has;
+    task.resize((size_t)total);
+    has.assign((size_t)total, 0);
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int nth = (int)std::min<int64_t>(std::min<unsigned>(hw, 16u), std::max<int64_t>(1, total / 2048));
     if (nth > 1 && (!c->pool || c->pool->size() < nth)) c->pool.reset(new WorkerPool(nth));
@@ -1165,11 +1189,19 @@ bool scen_ready(const Scen &s) { return s.dem_level >= 0 && !s.leaves.empty(); }
 // the scenario totals (leaf order) and clear them
 int fold_accumulators(gf_ctx *c)
 {
-    std::vector<double> ca((size_t)c->cap), ba((size_t)c->cap), cb((size_t)c->cap), bb((size_t)c->cap);
-    HIPCHK(c, hipMemcpyAsync(ca.data(), c->cacc[0], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(cb.data(), c->cacc[1], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(ba.data(), c->bacc[0], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(bb.data(), c->bacc[1], sizeof(double) * ca.size(), hipMemcpyDeviceToHost, c->stream));
+    const size_t cap = (size_t)c->cap;
+    c->fold_buf.resize(4 * cap);
+    double *ca = c->fold_buf.data(), *cb = ca + cap, *ba = cb + cap, *bb = ba + cap;
+    HIPCHK(c, hipMemcpyAsync(ca, c->cacc[0], sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cb, c->cacc[1], sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ba, c->bacc[0], sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bb, c->bacc[1], sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
+    // the clears are queued behind the copies; later device work is ordered
+    // after them on the same stream, so the host need not wait for them
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(c, hipMemsetAsync(c->cacc[k], 0, sizeof(double) * cap, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->bacc[k], 0, sizeof(double) * cap, c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (size_t si = 0; si < c->sc.size(); ++si) {
         Scen &s = c->sc[si];
@@ -1179,11 +1211,6 @@ int fold_accumulators(gf_ctx *c)
             s.bnd_base += cur ? bb[(size_t)L.slot] : ba[(size_t)L.slot];
         }
     }
-    for (int k = 0; k < 2; ++k) {
-        HIPCHK(c, hipMemsetAsync(c->cacc[k], 0, sizeof(double) * (size_t)c->cap, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->bacc[k], 0, sizeof(double) * (size_t)c->cap, c->stream));
-    }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     return GF_OK;
 }
 
@@ -1864,7 +1891,7 @@ namespace {
 struct Topo {
     const gf_ctx *c;
     const Scen *s;
-    LeafMap internal;                         // keys of nodes that have children
+    LeafMap &internal;                        // keys of nodes that have children
     bool inside(int l, int64_t X, int64_t Y) const
     {
         return X >= 0 && Y >= 0 && X < ((int64_t)s->d.mi << l) && Y < ((int64_t)s->d.mj << l);
@@ -1908,19 +1935,33 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
     std::vector<XferTaskH> xfer;
     std::vector<int32_t> freed;
     int64_t off = 0, total = 0;
+    bool changed = false;   // a leaf was refined or coarsened in some scenario
     for (size_t si = 0; si < c->sc.size(); ++si) {
         Scen &s = c->sc[si];
         const int64_t n = (int64_t)s.leaves.size();
         const int8_t *fl = flags + off;
         off += n;
-        std::vector<char> ref((size_t)n, 0), coa((size_t)n, 0);
+        // a scenario where no flag can take effect keeps its leaves (the
+        // common case between fronts): none of the work below is needed
+        bool cand = false;
+        for (int64_t k = 0; k < n && !cand; ++k) {
+            const int lv = s.leaves[(size_t)k].level;
+            cand = (fl[k] > 0 && lv < s.d.max_level) || (fl[k] < 0 && lv > s.d.min_level);
+        }
+        if (!cand) {
+            total += n;
+            continue;
+        }
+        std::vector<char> &ref = c->rg_ref, &coa = c->rg_coa;
+        ref.assign((size_t)n, 0);
+        coa.assign((size_t)n, 0);
         for (int64_t k = 0; k < n; ++k) ref[(size_t)k] = fl[k] > 0 && s.leaves[(size_t)k].level < s.d.max_level;
         // 2:1 face+corner balance closure of the refinement: a leaf must
         // refine when one of the twelve next-finer cells around it has
         // children.  The mesh was balanced before, so only a leaf one level
         // coarser than, and next to, a node that gains children can break
         // the rule; the closure follows a worklist of such nodes.
-        Topo T{c, &s, {}};
+        Topo T{c, &s, c->rg_internal};
         T.internal.reset((size_t)n);
         struct Node { int l; int64_t X, Y; };
         std::vector<Node> work;
@@ -1965,16 +2006,24 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
             if (T.finer_than_next(L.level - 1, L.PI >> 1, L.PJ >> 1)) continue;
             for (int q = 0; q < 4; ++q) coa[(size_t)sib[q]] = 1;
         }
+        bool any = false;
+        for (int64_t k = 0; k < n && !any; ++k) any = ref[(size_t)k] || coa[(size_t)k];
+        if (!any) {
+            total += n;
+            continue;
+        }
+        changed = true;
         // new leaves; slots for children and parents are fresh
-        std::vector<Leaf> nl;
+        std::vector<Leaf> &nl = c->rg_leaves;
         std::vector<Leaf *> fresh;
-        nl.reserve((size_t)n + 3 * (size_t)n);
         int64_t need = 0;
         for (int64_t k = 0; k < n; ++k) need += ref[(size_t)k] ? 4 : 0;
+        nl.clear();
+        nl.reserve((size_t)n + (size_t)need);
         for (int64_t k = 0; k < n; ++k) need += (coa[(size_t)k] && !(s.leaves[(size_t)k].PI & 1) && !(s.leaves[(size_t)k].PJ & 1)) ? 1 : 0;
         if (need > (int64_t)c->free_slots.size()) return fail(c, GF_E_NOMEM, "patch pool too small for the regrid");
-        struct Pending { int kind; int64_t src; int q; };
-        std::vector<Pending> pend;
+        std::vector<RgPending> &pend = c->rg_pend;
+        pend.clear();
         for (int64_t k = 0; k < n; ++k) {
             const Leaf &L = s.leaves[(size_t)k];
             if (ref[(size_t)k]) {
@@ -2000,7 +2049,7 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
         const auto &oldmap = s.map;
         // transfer tasks (read the old slots, write the fresh ones)
         for (size_t j = 0; j < nl.size(); ++j) {
-            const Pending &p = pend[j];
+            const RgPending &p = pend[j];
             if (p.kind == 2) continue;
             fresh.push_back(&nl[j]);
             XferTaskH t{};
@@ -2017,9 +2066,16 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
         }
         rc = upload_bathy(c, s, fresh);
         if (rc) return rc;
-        s.leaves = std::move(nl);
+        s.leaves.swap(nl);   // the old list's memory serves the next regrid
         sort_leaves(c, s);
         total += (int64_t)s.leaves.size();
+    }
+    if (!changed) {
+        // the same leaves, slots, descriptors and reflux tasks: only the dry
+        // flags are recomputed, as after any regrid
+        c->flags_dirty = true;
+        if (n_leaves) *n_leaves = total;
+        return GF_OK;
     }
     if (!xfer.empty()) {
         if ((int64_t)xfer.size() > c->xfer_cap) {
@@ -2353,7 +2409,7 @@ int gf_net_predict(gf_ctx *c, int8_t *flags_out, int64_t cap, int64_t *n_out)
             if (f < 0 && L.level <= S.d.min_level) f = 0;
             flags[(size_t)k++] = f;
         }
-    c->last_flags = flags;
+    c->last_flags.assign(flags.begin(), flags.end());
     if (n_out) *n_out = n;
     if (flags_out) {
         if (cap < n) return fail(c, GF_E_INVALID, "flag buffer too small");
