@@ -1187,7 +1187,14 @@ bool scen_ready(const Scen &s) { return s.dem_level >= 0 && !s.leaves.empty(); }
 
 // fold the per-slot clamp/boundary accumulators of the current buffer into
 // the scenario totals (leaf order) and clear them
-int fold_accumulators(gf_ctx *c)
+// The fold of the per-slot budget accumulators into each scenario's base, in
+// two halves so that a regrid can do its topology work while the copies run:
+// fold_begin queues the device-to-host copies; fold_finish waits for them,
+// adds the current leaves' values (before the leaf list changes) and queues
+// the clears (later device work is ordered after them on the stream).  Until
+// fold_finish the device values are untouched, so an error in between loses
+// nothing.
+int fold_begin(gf_ctx *c)
 {
     const size_t cap = (size_t)c->cap;
     c->fold_buf.resize(4 * cap);
@@ -1196,12 +1203,13 @@ int fold_accumulators(gf_ctx *c)
     HIPCHK(c, hipMemcpyAsync(cb, c->cacc[1], sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(ba, c->bacc[0], sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(bb, c->bacc[1], sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
-    // the clears are queued behind the copies; later device work is ordered
-    // after them on the same stream, so the host need not wait for them
-    for (int k = 0; k < 2; ++k) {
-        HIPCHK(c, hipMemsetAsync(c->cacc[k], 0, sizeof(double) * cap, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->bacc[k], 0, sizeof(double) * cap, c->stream));
-    }
+    return GF_OK;
+}
+
+int fold_finish(gf_ctx *c)
+{
+    const size_t cap = (size_t)c->cap;
+    const double *ca = c->fold_buf.data(), *cb = ca + cap, *ba = cb + cap, *bb = ba + cap;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (size_t si = 0; si < c->sc.size(); ++si) {
         Scen &s = c->sc[si];
@@ -1211,7 +1219,17 @@ int fold_accumulators(gf_ctx *c)
             s.bnd_base += cur ? bb[(size_t)L.slot] : ba[(size_t)L.slot];
         }
     }
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(c, hipMemsetAsync(c->cacc[k], 0, sizeof(double) * cap, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->bacc[k], 0, sizeof(double) * cap, c->stream));
+    }
     return GF_OK;
+}
+
+int fold_accumulators(gf_ctx *c)
+{
+    const int rc = fold_begin(c);
+    return rc ? rc : fold_finish(c);
 }
 
 int check_scen(gf_ctx *c, int32_t scen)
@@ -1929,8 +1947,11 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
     const int64_t nw = (int64_t)c->desc.size();
     const int8_t *flags = flags_in ? flags_in : (c->last_flags.size() == (size_t)nw ? c->last_flags.data() : nullptr);
     if (!flags) return fail(c, GF_E_STATE, "no flags: call gf_tag first");
-    rc = fold_accumulators(c);
+    // the budget fold's copies run under the topology work below; it is
+    // finished before the first leaf list changes
+    rc = fold_begin(c);
     if (rc) return rc;
+    bool folded = false;
     const int m = c->m;
     std::vector<XferTaskH> xfer;
     std::vector<int32_t> freed;
@@ -2064,6 +2085,11 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
             }
             xfer.push_back(t);
         }
+        if (!folded) {
+            rc = fold_finish(c);
+            if (rc) return rc;
+            folded = true;
+        }
         rc = upload_bathy(c, s, fresh);
         if (rc) return rc;
         s.leaves.swap(nl);   // the old list's memory serves the next regrid
@@ -2073,6 +2099,8 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
     if (!changed) {
         // the same leaves, slots, descriptors and reflux tasks: only the dry
         // flags are recomputed, as after any regrid
+        rc = fold_finish(c);
+        if (rc) return rc;
         c->flags_dirty = true;
         if (n_leaves) *n_leaves = total;
         return GF_OK;
