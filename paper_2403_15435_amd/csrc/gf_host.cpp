@@ -550,11 +550,17 @@ int upload_bathy(gf_ctx *c, const Scen &s, const std::vector<Leaf *> &leaves)
 // common resolution of 2^20 inside the tree.  A regrid emits children in
 // place of their parent in quadrant order (x low bit) and a parent in place of
 // its first child, which keeps this order; the sort only runs when the list
-// is out of order (leaves set from outside).
-void sort_leaves(const gf_ctx *c, Scen &s)
+// is out of order (leaves set from outside).  in_order: the caller built the
+// list in this order (a regrid), and only the key map is rebuilt.
+void sort_leaves(const gf_ctx *c, Scen &s, bool in_order = false)
 {
     const int mi = s.d.mi;
     const size_t n = s.leaves.size();
+    if (in_order) {
+        s.map.reset(n);
+        for (size_t k = 0; k < n; ++k) s.map.set(key_of(s.leaves[k].level, s.leaves[k].PI, s.leaves[k].PJ), (int32_t)k);
+        return;
+    }
     // kept between calls (a regrid sorts the whole list each time)
     static thread_local std::vector<std::pair<int64_t, uint64_t>> key;
     key.resize(n);
@@ -2093,7 +2099,7 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
         rc = upload_bathy(c, s, fresh);
         if (rc) return rc;
         s.leaves.swap(nl);   // the old list's memory serves the next regrid
-        sort_leaves(c, s);
+        sort_leaves(c, s, true);   // emitted in order (see sort_leaves): the map only
         total += (int64_t)s.leaves.size();
     }
     if (!changed) {
