@@ -265,6 +265,8 @@ struct gf_ctx {
     void *b = nullptr, *bg = nullptr, *reg = nullptr, *ghost = nullptr;
     double *cacc[2] = {nullptr, nullptr}, *bacc[2] = {nullptr, nullptr};
     PatchDesc *d_desc = nullptr;
+    PatchDesc *d_fdesc = nullptr;   // descriptors whose dry flags a regrid refreshes
+    int64_t fdesc_cap = 0;
     int64_t desc_cap = 0;
     RefluxTask *d_reflux = nullptr;
     int64_t reflux_cap = 0;
@@ -314,7 +316,10 @@ struct gf_ctx {
     std::vector<char> rg_ref, rg_coa;
     LeafMap rg_internal;
     std::vector<RefluxTask> rb_task;
-    std::vector<char> rb_has;
+    std::vector<char> rb_has, rb_rebuilt;
+    // after a regrid: the rebuilt descriptors (new leaves, and leaves next to
+    // a change); only their dry flags and dry-update states are refreshed
+    std::vector<PatchDesc, PinnedAlloc<PatchDesc>> flag_desc;
     std::vector<double, PinnedAlloc<double>> fold_buf;
     // profiling: prof times the steps with an event pair per stretch of
     // launches (ev[0] before its first step, ev[1] before the next
@@ -735,9 +740,10 @@ int rebuild_work(gf_ctx *c)
     c->desc.resize((size_t)total);
     // a task entry is read only where has is set, which writes it first
     std::vector<RefluxTask> &task = c->rb_task;
-    std::vector<char> &has = c->rb_has;
+    std::vector<char> &has = c->rb_has, &rebuilt = c->rb_rebuilt;
     task.resize((size_t)total);
     has.assign((size_t)total, 0);
+    rebuilt.assign((size_t)total, 0);
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     const int nth = (int)std::min<int64_t>(std::min<unsigned>(hw, 16u), std::max<int64_t>(1, total / 2048));
     if (nth > 1 && (!c->pool || c->pool->size() < nth)) c->pool.reset(new WorkerPool(nth));
@@ -776,6 +782,7 @@ int rebuild_work(gf_ctx *c)
                 return;
             }
             has[(size_t)g] = ht;
+            rebuilt[(size_t)g] = 1;
         }
     };
     if (nth == 1) {
@@ -793,6 +800,10 @@ int rebuild_work(gf_ctx *c)
     c->reflux.clear();
     for (int64_t g = 0; g < total; ++g)
         if (has[(size_t)g]) c->reflux.push_back(task[(size_t)g]);
+    c->flag_desc.clear();
+    if (c->reuse)
+        for (int64_t g = 0; g < total; ++g)
+            if (rebuilt[(size_t)g]) c->flag_desc.push_back(c->desc[(size_t)g]);
     if ((int64_t)c->desc.size() > c->desc_cap) {
         if (c->d_desc) (void)hipFree(c->d_desc);
         if (c->d_flags) (void)hipFree(c->d_flags);
@@ -877,6 +888,36 @@ int refresh_dry_flags(gf_ctx *c)
                                   c->dry[1], c->d_dstab, c->cap, c->cfg.dry_tol, c->m, c->stream);
     if (e != hipSuccess) return fail(c, GF_E_HIP, "dry-flag launch: %s", hipGetErrorString(e));
     c->flags_dirty = false;
+    return GF_OK;
+}
+
+// After a regrid: the dry flags and dry-update states of the patches whose
+// descriptor was rebuilt.  A leaf that kept its slot and its descriptor keeps
+// its state, its flag and, since reflux registers are numbered by slot, the
+// face records its last dry updates wrote; a new leaf (state moved in by the
+// transfer) or one next to a change needs them afresh.  The same kernel as
+// the full refresh, over a compact copy of those descriptors.
+int refresh_dry_flags_rebuilt(gf_ctx *c)
+{
+    const int64_t n = (int64_t)c->flag_desc.size();
+    if (c->flags_dirty || n == 0) return GF_OK;   // a full refresh is due anyway, or nothing changed
+    if (n > c->fdesc_cap) {
+        if (c->d_fdesc) (void)hipFree(c->d_fdesc);
+        c->d_fdesc = nullptr;
+        c->fdesc_cap = 0;
+        const int64_t want = std::max<int64_t>(n, 256);
+        HIPCHK(c, hipMalloc(&c->d_fdesc, sizeof(PatchDesc) * (size_t)want));
+        c->fdesc_cap = want;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_fdesc, c->flag_desc.data(), sizeof(PatchDesc) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    hipError_t e;
+    if (c->prec == GF_FP32)
+        e = gf_launch_dryflag_f32(c->d_fdesc, (int)n, c->d_scen, (const float *)c->q[0], (const float *)c->q[1], c->dry[0],
+                                  c->dry[1], c->d_dstab, c->cap, tau32(c->cfg.dry_tol), c->m, c->stream);
+    else
+        e = gf_launch_dryflag_f64(c->d_fdesc, (int)n, c->d_scen, (const double *)c->q[0], (const double *)c->q[1], c->dry[0],
+                                  c->dry[1], c->d_dstab, c->cap, c->cfg.dry_tol, c->m, c->stream);
+    if (e != hipSuccess) return fail(c, GF_E_HIP, "dry-flag launch: %s", hipGetErrorString(e));
     return GF_OK;
 }
 
@@ -1436,7 +1477,7 @@ void gf_destroy(gf_ctx *c)
                   c->d_queue, c->dry[0], c->dry[1], c->d_wet, c->d_wet_count, c->d_pitems, c->d_pnan,
                   c->d_prange, c->d_pmax, c->d_pres, c->d_bstage, c->d_bslots, c->d_dstab, c->d_stats,
                   c->d_sstage, c->d_sslots, c->d_gauges, c->d_grec, c->d_gcount, c->d_snap, c->d_snap_acc,
-                  c->d_lperm};
+                  c->d_lperm, c->d_fdesc};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     void *pn[] = {c->net.w, c->net.m, c->net.v, c->net.g, c->net.wb, c->net.x, c->net.y, c->net.logits, c->net.loss,
@@ -2103,11 +2144,10 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
         total += (int64_t)s.leaves.size();
     }
     if (!changed) {
-        // the same leaves, slots, descriptors and reflux tasks: only the dry
-        // flags are recomputed, as after any regrid
+        // the same leaves, slots, descriptors, reflux tasks, dry flags and
+        // dry-update states
         rc = fold_finish(c);
         if (rc) return rc;
-        c->flags_dirty = true;
         if (n_leaves) *n_leaves = total;
         return GF_OK;
     }
@@ -2140,9 +2180,10 @@ int gf_regrid(gf_ctx *c, const int8_t *flags_in, int64_t *n_leaves)
     c->reuse = true;
     for (int32_t sl : freed) give_slot(c, sl);
     c->topo_dirty = true;
-    c->flags_dirty = true;
     rc = ensure_work(c);
     c->reuse = false;
+    if (rc) return rc;
+    rc = refresh_dry_flags_rebuilt(c);
     if (rc) return rc;
     if (n_leaves) *n_leaves = total;
     return GF_OK;
