@@ -1602,7 +1602,9 @@ static int patch_io(gf_ctx *c, int32_t scen, int64_t leaf, int32_t field, double
         else to_real<double>(buf, (double *)tmp.data(), MM);
         HIPCHK(c, hipMemcpyAsync(dev, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (field == 0) c->flags_dirty = true;
+        // depth sets the dry flags; a written momentum must also end a stable
+        // dry patch's skipped updates (a dry update zeroes it)
+        if (field <= 2) c->flags_dirty = true;
     } else {
         HIPCHK(c, hipMemcpyAsync(tmp.data(), dev, tmp.size(), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
