@@ -39,22 +39,28 @@ inline uint64_t key_of(int level, int64_t PI, int64_t PJ)
 }
 
 // Leaf key -> leaf index: open addressing with linear probing, capacity a
-// power of two kept at least twice the entries (keys never equal the empty
-// mark: their top byte is level + 1 <= 15).
+// power of two kept at least twice the entries.  Key and value share an
+// entry (one cache line per probe), and an entry is live only when it carries
+// the current generation, so that clearing the map (once per regrid, for the
+// whole leaf list) costs nothing until the generation counter wraps.  The map
+// is never iterated: its layout cannot change a result.
 class LeafMap {
-    std::vector<uint64_t> keys_;
-    std::vector<int32_t> vals_;
+    struct Entry {
+        uint64_t key;
+        int32_t val;
+        uint32_t gen;
+    };
+    std::vector<Entry> tab_;
     size_t mask_ = 0, size_ = 0;
-    static constexpr uint64_t EMPTY = ~0ull;
+    uint32_t gen_ = 1;
     void grow()
     {
-        std::vector<uint64_t> k;
-        std::vector<int32_t> v;
-        k.swap(keys_);
-        v.swap(vals_);
+        std::vector<Entry> old;
+        old.swap(tab_);
+        const uint32_t g = gen_;
         reset(2 * size_ + 16);
-        for (size_t i = 0; i < k.size(); ++i)
-            if (k[i] != EMPTY) set(k[i], v[i]);
+        for (const Entry &e : old)
+            if (e.gen == g) set(e.key, e.val);
     }
     static uint64_t mix(uint64_t k)
     {
@@ -69,19 +75,28 @@ public:
     {
         size_t cap = 16;
         while (cap < 2 * n + 2) cap <<= 1;
-        keys_.assign(cap, EMPTY);
-        vals_.assign(cap, -1);
+        if (cap != tab_.size()) {
+            tab_.assign(cap, Entry{0, -1, 0});
+            gen_ = 1;
+        } else if (++gen_ == 0) {
+            std::fill(tab_.begin(), tab_.end(), Entry{0, -1, 0});
+            gen_ = 1;
+        }
         mask_ = cap - 1;
         size_ = 0;
     }
     void set(uint64_t k, int32_t v)
     {
-        if (2 * (size_ + 1) > keys_.size()) grow();
+        if (2 * (size_ + 1) > tab_.size()) grow();
         size_t i = mix(k) & mask_;
-        while (keys_[i] != EMPTY && keys_[i] != k) i = (i + 1) & mask_;
-        if (keys_[i] == EMPTY) ++size_;
-        keys_[i] = k;
-        vals_[i] = v;
+        while (tab_[i].gen == gen_ && tab_[i].key != k) i = (i + 1) & mask_;
+        Entry &e = tab_[i];
+        if (e.gen != gen_) {
+            ++size_;
+            e.gen = gen_;
+            e.key = k;
+        }
+        e.val = v;
     }
     // insert k (value 1) if absent; true if it was absent
     bool insert(uint64_t k)
@@ -94,10 +109,11 @@ public:
     // -1 when absent
     int32_t get(uint64_t k) const
     {
-        if (keys_.empty()) return -1;
+        if (tab_.empty()) return -1;
         for (size_t i = mix(k) & mask_;; i = (i + 1) & mask_) {
-            if (keys_[i] == k) return vals_[i];
-            if (keys_[i] == EMPTY) return -1;
+            const Entry &e = tab_[i];
+            if (e.gen != gen_) return -1;
+            if (e.key == k) return e.val;
         }
     }
 };
