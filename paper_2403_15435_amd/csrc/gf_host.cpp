@@ -820,7 +820,9 @@ int rebuild_work(gf_ctx *c)
     if (c->reuse)
         for (int64_t g = 0; g < total; ++g)
             if (rebuilt[(size_t)g]) c->flag_desc.push_back(c->desc[(size_t)g]);
+    bool fresh_alloc = false;
     if ((int64_t)c->desc.size() > c->desc_cap) {
+        fresh_alloc = true;
         if (c->d_desc) (void)hipFree(c->d_desc);
         if (c->d_flags) (void)hipFree(c->d_flags);
         if (c->d_mass) (void)hipFree(c->d_mass);
@@ -834,8 +836,16 @@ int rebuild_work(gf_ctx *c)
         c->reflux_cap = std::max<int64_t>((int64_t)c->reflux.size(), 256);
         HIPCHK(c, hipMalloc(&c->d_reflux, sizeof(RefluxTask) * (size_t)c->reflux_cap));
     }
-    if (!c->desc.empty())
-        HIPCHK(c, hipMemcpyAsync(c->d_desc, c->desc.data(), sizeof(PatchDesc) * c->desc.size(), hipMemcpyHostToDevice, c->stream));
+    // after a regrid the descriptors before the first one that was rebuilt or
+    // changed index are the bytes the device already holds (a regrid inserts
+    // and removes leaves at a few places of an ordered list): only the rest
+    // is uploaded
+    int64_t kept = 0;
+    if (c->reuse && !fresh_alloc)
+        while (kept < total && !rebuilt[(size_t)kept] && c->old_at[(size_t)c->desc[(size_t)kept].slot] == kept) ++kept;
+    if (kept < total)
+        HIPCHK(c, hipMemcpyAsync(c->d_desc + kept, c->desc.data() + kept, sizeof(PatchDesc) * (size_t)(total - kept),
+                                 hipMemcpyHostToDevice, c->stream));
     if (!c->reflux.empty())
         HIPCHK(c, hipMemcpyAsync(c->d_reflux, c->reflux.data(), sizeof(RefluxTask) * c->reflux.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
