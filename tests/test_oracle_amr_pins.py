@@ -206,7 +206,8 @@ def test_amr_band_against_ritter(oracle_mod):
     dam (x in [750, 1500] m: level 4 inside, level 3 outside).  The
     rarefaction crosses both coarse/fine faces.  Inside the band the
     adaptive run differs from the uniform level-4 run by at most twice the
-    uniform run's own error against the closed form (the survey's pin), the
+    uniform run's own error against the closed form (Section 4: refinement
+    must not cost accuracy where the fine level covers the flow), the
     solution stays y-invariant bit for bit with no transverse momentum, and
     the volume budget closes."""
     band = (750.0, 1500.0)
