@@ -960,6 +960,7 @@ void fill_step_args(gf_ctx *c, StepArgs<T> &a, double dt_fixed, int mode, T tau)
     a.tau = tau; a.tau64 = c->cfg.dry_tol; a.done_counter = c->d_counter;
     a.queue = c->d_queue; a.persistent = 0; a.dry0 = c->dry[0]; a.dry1 = c->dry[1];
     a.wet_list = c->d_wet; a.wet_count = c->d_wet_count;
+    a.dry_count = c->d_wet_count + 8;   // same 64-byte allocation, another 32-byte sector
     a.dstab = c->d_dstab; a.stats = c->prof_stats ? c->d_stats : nullptr;
 }
 

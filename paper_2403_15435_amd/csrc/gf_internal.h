@@ -115,6 +115,11 @@ struct StepArgs {
     uint8_t *dry0, *dry1;        // per slot and buffer: 1 iff every interior cell has h <= tau
     int32_t *wet_list;           // work items dry_kernel left for step_kernel
     unsigned int *wet_count;     // their number; reset to 0 by the last workgroup of step_kernel
+    // patches dry_kernel found needing the dry update, for dry_update_kernel:
+    // kept in wet_list from its far end (entry k at cap - 1 - k; wet and dry
+    // entries together are at most the patch count), their number reset with
+    // wet_count
+    unsigned int *dry_count;
     // per slot: 0 unknown; 1 + 2c: the last update was a full dry update
     // reading buffer c; 4 stable: both buffers hold the same dry state, a
     // fixed point of the dry update (which then writes nothing)
